@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Throughput of the Lagrangian-point tracking step on one MI355X.
+
+One step = host-cell search + interpolation + spreading of every point of the
+workload (8 bubbles' markers and 10^7 uniform particles on a band-refined
+l 7->10 octree, FP32, fixed-point spreading) in one batched persistent pass
+replayed from a HIP graph.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: points/s, the dominant kernel's achieved bandwidth
+against the HBM peak (roofline), the FP64 oracle timed on a bounded sample on
+the host cores (cpu_baseline), and side measurements (tree build, plain FP64
+GPU path, spreading modes, error against the oracle).
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "Lagrangian points located+interpolated+spread /s"
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_k_batch_cfg2.json")
+
+# Algorithmic bytes (compulsory I/O, each input read once, each output
+# written once): per point pos + id + vel + force; per touched leaf its key
+# and level, its field row and its spread row.
+BYTES_PER_POINT = {"f32": 12 + 4 + 12 + 12, "f64": 24 + 4 + 24 + 24}
+BYTES_PER_LEAF = {"f32": 9 + 12 + 12, "f64": 9 + 24 + 24}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2605_20565_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload_desc(w, cfg):
+    lv = np.bincount(w.tree.levels, minlength=w.tree.l_max + 1)[w.tree.l_min:]
+    return {
+        "workload": f"cfg{cfg}",
+        "tree": f"band-refined octree l {w.tree.l_min}->{w.tree.l_max}, {w.tree.n_leaves} leaves "
+                f"(per level {lv.tolist()}), periodic unit cube",
+        "points": int(w.n_points),
+        "instances": int(len(w.instances) - 1),
+        "markers": int(sum(w.instances[i + 1] - w.instances[i] for i, k in enumerate(w.kinds) if k == "markers")),
+        "ops": "locate+interpolate+spread",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--scale", type=float, default=1.0, help="multiplies the particle count")
+    ap.add_argument("--dtype", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--mode", choices=["fixed", "atomic"], default="fixed")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="points in the oracle's timed sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip side measurements")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding paragraph of the design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    import paper_2605_20565_amd as ot
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dt = torch.float32 if args.dtype == "f32" else torch.float64
+
+    t0 = time.time()
+    w = synth.workload(args.config, scale=args.scale)
+    log(f"[bench] workload cfg{args.config}: {w.tree.n_leaves} leaves, {w.n_points} points "
+        f"({time.time() - t0:.1f}s to generate)")
+
+    # ---- inputs resident in HBM --------------------------------------------
+    anchors = torch.from_numpy(w.tree.anchors.astype(np.int32)).to(dev)
+    levels = torch.from_numpy(w.tree.levels).to(dev)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    tree = ot.Tree.from_anchors(anchors, levels, w.tree.l_min, w.tree.l_max, w.tree.periodic)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - tb) * 1e3
+    info = tree.info()
+    log(f"[bench] tree built in {build_ms:.1f} ms; table {info.table_levels} levels, {info.table_bytes / 2**20:.1f} MiB")
+
+    pos = torch.from_numpy(w.points).to(dev, dt)
+    force = torch.from_numpy(w.forces).to(dev, dt)
+    field = tree.permute_rows(torch.from_numpy(w.field).to(dev, dt))
+    n = pos.shape[0]
+    ids = torch.empty(n, dtype=torch.int32, device=dev)
+    vel = torch.empty((n, 3), dtype=dt, device=dev)
+    fout = torch.empty((tree.n_leaves, 3), dtype=dt, device=dev)
+    offsets = [int(v) for v in w.instances]
+    ops = [ot.OT_OP_LOCATE | ot.OT_OP_INTERPOLATE | ot.OT_OP_SPREAD] * (len(offsets) - 1)
+    plan = ot.BatchPlan(tree, offsets, ops, dtype=dt, mode=args.mode, block=args.block, tile=args.tile,
+                        grid=args.grid)
+    n_tiles, grid = plan.shape()
+
+    def step():
+        plan.run(pos, field=field, force=force, ids=ids, vel=vel, field_out=fout)
+
+    # ---- timed region: K graph replays back to back -------------------------
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = n * args.steps / elapsed
+    log(f"[bench] {ms_per_step:.3f} ms/step, {value:.4g} points/s")
+
+    # ---- dominant kernel duration: HIP events around it inside the graph ----
+    plan.set_timing(True)
+    step()
+    torch.cuda.synchronize()
+    kms = []
+    for _ in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        kms.append(plan.last_kernel_ms())
+    plan.set_timing(False)
+    kernel_ms = float(np.mean(kms))
+
+    # touched leaves: leaves that receive a weight from at least one point
+    ones = torch.ones_like(pos)
+    touched = int(torch.count_nonzero(tree.spread(ones, pos, mode="atomic").abs().sum(dim=1)).item())
+    alg_bytes = n * BYTES_PER_POINT[args.dtype] + touched * BYTES_PER_LEAF[args.dtype]
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_source_hash() and tr.get("dtype") == args.dtype \
+                and tr.get("mode") == args.mode and tr.get("config") == args.config:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "k_batch", "kernel_ms": round(kernel_ms, 4), "algorithmic_bytes": int(alg_bytes),
+                "touched_leaves": touched}
+    log(f"[bench] k_batch {kernel_ms:.3f} ms, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBPS:.1%} of peak)")
+
+    extra = {}
+    if not args.no_extra:
+        extra = side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot, torch)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
+        "config": {**workload_desc(w, args.config), "precision": args.dtype, "spread_mode": args.mode,
+                   "path": "batched persistent kernel, HIP graph", "tiles": n_tiles, "workgroups": grid},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    out.update(extra)
+    out["build_tree_ms"] = round(build_ms, 2)
+    out["kernel_source"] = kernel_source_hash()
+    print(json.dumps(out), flush=True)
+
+
+def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot, torch):
+    res = {}
+    n = pos.shape[0]
+
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) * 1e3 / reps
+
+    # plain FP64 GPU path (one fused launch, FP64 atomics), the speedup's denominator
+    p64 = torch.from_numpy(w.points).to(dev, torch.float64)
+    f64 = torch.from_numpy(w.forces).to(dev, torch.float64)
+    fl64 = tree.permute_rows(torch.from_numpy(w.field).to(dev, torch.float64))
+    i64 = torch.empty(n, dtype=torch.int32, device=dev)
+    v64 = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    o64 = torch.empty((tree.n_leaves, 3), dtype=torch.float64, device=dev)
+    ms64 = timeit(lambda: tree.track(p64, field=fl64, force=f64, mode="atomic", ids=i64, vel=v64, field_out=o64),
+                  max(3, args.steps // 2))
+    res["fp64_plain"] = {"ms_per_step": round(ms64, 4), "value": n / (ms64 * 1e-3), "spread_mode": "atomic",
+                         "path": "one fused launch per step"}
+    ms_main = timeit(step, max(3, args.steps // 2))
+    res["speedup_vs_fp64_plain"] = round(ms64 / ms_main, 3)
+    del p64, f64, fl64, i64, v64, o64
+
+    # spreading modes on the batched FP32 path
+    modes = {}
+    for mode in ("fixed", "atomic"):
+        pl = ot.BatchPlan(tree, [int(v) for v in w.instances], [7] * (len(w.instances) - 1), dtype=dt, mode=mode,
+                          block=args.block, tile=args.tile, grid=args.grid)
+        ids = torch.empty(n, dtype=torch.int32, device=dev)
+        vel = torch.empty((n, 3), dtype=dt, device=dev)
+        fo = torch.empty((tree.n_leaves, 3), dtype=dt, device=dev)
+        modes[mode] = round(timeit(lambda: pl.run(pos, field=field, force=force, ids=ids, vel=vel, field_out=fo),
+                                   max(3, args.steps // 2)), 4)
+        pl.close()
+    res["spread_mode_ms_per_step"] = modes
+
+    # copy bandwidth for context
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    cms = timeit(lambda: b.copy_(a), 10)
+    res["copy_GBps"] = round(2 * a.numel() * 4 / (cms * 1e-3) / 1e9, 1)
+    del a, b
+
+    # error against the oracle on a sample of the same inputs
+    res["error_vs_oracle"] = oracle_check(w, tree, dev, dt, torch)
+    return res
+
+
+def oracle_check(w, tree, dev, dt, torch, n_sample=20000):
+    import oracle
+    rng = np.random.default_rng(123)
+    sel = np.sort(rng.choice(w.n_points, size=min(n_sample, w.n_points), replace=False))
+    npdt = np.float32 if dt == torch.float32 else np.float64
+    pts = w.points[sel].astype(npdt).astype(np.float64)
+    frc = w.forces[sel].astype(npdt).astype(np.float64)
+    o = oracle.Tree.from_anchors(w.tree.anchors, w.tree.levels, w.tree.l_min, w.tree.l_max, w.tree.periodic)
+    fld = o.permute_rows(w.field).astype(npdt).astype(np.float64)
+    P, F, Fd = (torch.from_numpy(x).to(dev, dt) for x in (pts, frc, fld))
+    ids, vel, fo = tree.track(P, field=Fd, force=F, mode="fixed")
+    U, S = o.interpolate(fld, pts, with_scale=True)
+    f, Sf, _ = o.spread(frc, pts, with_scale=True)
+    eu = np.abs(vel.cpu().numpy() - U) / np.maximum(S, 1e-300)
+    ef = np.abs(fo.cpu().numpy() - f) / np.maximum(Sf, 1e-300)
+    touched = Sf > 0
+    return {"sample": int(len(sel)), "ids_mismatch": int((ids.cpu().numpy() != o.locate(pts)).sum()),
+            "interp_scaled_max": float(eu.max()), "spread_scaled_max": float(ef[touched].max()),
+            "spread_scaled_p99": float(np.percentile(ef[touched], 99))}
+
+
+def cpu_baseline(w, n_sample):
+    """The FP64 oracle (plain C, OpenMP over points for search and
+    interpolation, serial spreading) on a bounded sample of the workload."""
+    import oracle
+    o = oracle.Tree.from_anchors(w.tree.anchors, w.tree.levels, w.tree.l_min, w.tree.l_max, w.tree.periodic)
+    fld = o.permute_rows(w.field)
+    rng = np.random.default_rng(7)
+    m = min(n_sample, w.n_points)
+    sel = np.sort(rng.choice(w.n_points, size=m, replace=False))
+    pts = np.ascontiguousarray(w.points[sel])
+    frc = np.ascontiguousarray(w.forces[sel])
+    t = time.perf_counter()
+    o.locate(pts)
+    o.interpolate(fld, pts)
+    o.spread(frc, pts)
+    el = time.perf_counter() - t
+    log(f"[bench] oracle: {m} points in {el:.1f}s on {oracle.num_threads()} threads")
+    return {"value": m / el, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{m} points drawn uniformly from the {w.n_points}-point workload, full tree; "
+                      f"locate+interpolate+spread in FP64, {el:.1f}s"}
+
+
+if __name__ == "__main__":
+    main()

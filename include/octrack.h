@@ -1,0 +1,212 @@
+/*
+ * octrack.h -- C ABI of the MI355X (gfx950) Lagrangian-point tracking library.
+ *
+ * The library implements the Lagrangian-point tracking step of an immersed-
+ * boundary / lattice-Boltzmann solver on an adaptive octree (Jiang,
+ * Calzavarini & Krug, "Simulations of particle-laden flows with large
+ * dispersed-phase size disparities using highly scalable parallel adaptive
+ * methods"):
+ *   - the octree as an array of leaves sorted by Morton (Z-order) index
+ *     (Sec. 3.1, grid management);
+ *   - host-cell search: every Lagrangian point is associated with the leaf
+ *     that contains it (Sec. 3.2; Algorithm 1, search_host_cell);
+ *   - interpolation of the leaf velocity field to the points and spreading of
+ *     point forces back to the leaves with the 3-point regularized delta
+ *     function (Sec. 2.2, the interpolation, spreading, W and phi equations).
+ *
+ * Conventions (all calls):
+ *   - Domain: the unit cube, one root tree.  A leaf at level l with integer
+ *     anchor a (units of 2^-L, L = l_max) is the half-open box
+ *     [a, a + 2^(L-l)) on each axis.
+ *   - Morton key of an anchor (x, y, z): bit b of x goes to bit 3b, of y to
+ *     3b+1, of z to 3b+2.  Keys use 3L bits; L <= 21.
+ *   - Leaf ids are ranks in the Morton-sorted leaf array (0 .. n_leaves-1).
+ *     A point without a host leaf (NaN, outside a non-periodic domain,
+ *     |x 2^L| >= 2^52) gets id -1; interpolate returns 0 for it and spread
+ *     skips it.  That is not an error.
+ *   - Integer coordinates of a point are floor(x 2^L) computed in FP64 for
+ *     both precisions; periodic domains wrap them modulo 2^L.
+ *   - Stencil: 3x3x3 level-l cells around the host cell, l = host leaf level;
+ *     the value at a stencil node is the value of the leaf containing the
+ *     node's centre; weight = phi(rx) phi(ry) phi(rz) (no cell-volume factor,
+ *     so spread is the exact transpose of interpolate).  Non-periodic: nodes
+ *     outside the cube are dropped.
+ *   - pos, field, vel, force, grad arrays are row-major (rows, 3) in the
+ *     dtype given (OT_F32 = float, OT_F64 = double), device memory.
+ *   - Every pointer argument that names an array is a DEVICE pointer unless
+ *     stated "host".  All arrays are owned by the caller; the library never
+ *     frees them and keeps no reference after the call returns (except the
+ *     batch plan, see below).
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls enqueue work
+ *     and return; results are ready when the stream reaches them.  Only
+ *     ot_build_tree synchronises (once, to report validation errors).
+ *   - Return value: OT_OK (0) or a negative OT_ERR_* code; ot_last_error()
+ *     returns a message for the calling thread's last failure.
+ */
+#ifndef OCTRACK_H
+#define OCTRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OT_OK                 0
+#define OT_ERR_INVALID       -1   /* bad argument (null pointer, n < 0, bad enum, ...)      */
+#define OT_ERR_NOT_PARTITION -2   /* leaves do not tile the unit cube exactly                */
+#define OT_ERR_UNSORTED_DUP  -3   /* two leaves share a Morton key                           */
+#define OT_ERR_LEVEL_RANGE   -4   /* L > 21, l_min > L, a leaf level outside [l_min, L] or a */
+                                  /* key with bits above 3L                                  */
+#define OT_ERR_OOM           -5   /* device allocation failed                                */
+#define OT_ERR_HIP           -6   /* a HIP runtime call failed                               */
+#define OT_ERR_CAPACITY      -7   /* more leaves than the id field holds (2^26)              */
+
+#define OT_F32 0
+#define OT_F64 1
+
+/* Spreading accumulation.  ATOMIC: atomic adds in the working precision
+ * (FP32 or FP64), order dependent in the last bits.  FIXED: every
+ * contribution fl(w F) is rounded once to a signed 64-bit fixed-point value
+ * q = rint(fl(w F) 2^s) and summed with integer atomics, so the result does
+ * not depend on execution order (bitwise reproducible).  s = 62 - E where
+ * 2^E >= n * max|F| (so no leaf sum can overflow); the absolute error per
+ * contribution is at most 2^-(s+1). */
+#define OT_SPREAD_ATOMIC 0
+#define OT_SPREAD_FIXED  1
+
+/* Operations of a fused / batched pass (bit flags). */
+#define OT_OP_LOCATE      1   /* write host ids                       */
+#define OT_OP_INTERPOLATE 2   /* write interpolated velocities        */
+#define OT_OP_SPREAD      4   /* spread forces into the leaf field    */
+
+typedef struct ot_tree ot_tree;
+typedef struct ot_batch_plan ot_batch_plan;
+
+typedef struct {
+    int32_t l_min;     /* coarsest leaf level (>= 0)                                  */
+    int32_t l_max;     /* finest leaf level L (<= 21); integer coordinates in 2^-L    */
+    int32_t periodic;  /* 1: the unit cube is periodic on all three axes               */
+} ot_tree_desc;
+
+typedef struct {
+    int64_t n_leaves;
+    int32_t l_min, l_max, periodic;
+    int32_t table_levels;    /* levels of the descent table (root + sub-tables)      */
+    int64_t table_bytes;     /* device bytes of the descent table                    */
+    int64_t workspace_bytes; /* device bytes of the fixed-point spreading workspace   */
+} ot_tree_info;
+
+/* Tuning of the batched persistent pass. Zero fields take defaults. */
+typedef struct {
+    int32_t block;        /* threads per workgroup (multiple of 64, <= 1024)          */
+    int32_t tile;         /* points per tile (multiple of block)                      */
+    int32_t grid;         /* persistent workgroups; 0 = as many as fit on the chip    */
+    int32_t reserved;
+} ot_tuning;
+
+/* Morton keys of leaf anchors (Sec. 3.1: leaves are ordered along the
+ * Z-curve).  anchors: (n, 3) uint32, each < 2^l_max.  keys: (n,) uint64.
+ * Errors: OT_ERR_INVALID (null with n > 0, n < 0), OT_ERR_LEVEL_RANGE
+ * (l_max outside [0, 21]).  Anchors >= 2^l_max are not checked here;
+ * ot_build_tree rejects the resulting keys. */
+int ot_encode_keys(const uint32_t *anchors, int64_t n, int32_t l_max, uint64_t *keys,
+                   void *stream);
+
+/* Build the searchable tree from its leaves (the Z-sorted leaf array of
+ * Sec. 3.1 and Algorithm 1, plus a descent table that resolves 3 levels per
+ * lookup).  keys: (n_leaves,) Morton keys of the anchors at l_max resolution,
+ * any order; levels: (n_leaves,) uint8.  perm_out (nullable, (n_leaves,)
+ * int32): perm_out[id] = input row of the leaf with that id, so callers can
+ * reorder their leaf fields once.  On success *out receives a handle that
+ * owns device copies of everything it needs; the inputs may be freed.
+ * Errors: OT_ERR_INVALID, OT_ERR_LEVEL_RANGE, OT_ERR_NOT_PARTITION,
+ * OT_ERR_UNSORTED_DUP, OT_ERR_CAPACITY, OT_ERR_OOM, OT_ERR_HIP.  Synchronises
+ * `stream` once. */
+int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_t n_leaves,
+                  const ot_tree_desc *desc, int32_t *perm_out, void *stream, ot_tree **out);
+
+/* Release a tree (waits for the device to finish using it). */
+int ot_destroy_tree(ot_tree *tree);
+
+/* Sizes and parameters of a tree (host struct). */
+int ot_tree_info_get(const ot_tree *tree, ot_tree_info *info);
+
+/* Copy the sorted leaf keys (uint64) and levels (uint8) out; either pointer
+ * may be NULL. */
+int ot_tree_leaves(const ot_tree *tree, uint64_t *keys_out, uint8_t *levels_out, void *stream);
+
+/* Host-cell search (Sec. 3.2, Algorithm 1): ids[k] = leaf containing
+ * pos[k], or -1.  pos: (n, 3) dtype; ids: (n,) int32. */
+int ot_locate(const ot_tree *tree, const void *pos, int32_t dtype, int64_t n, int32_t *ids,
+              void *stream);
+
+/* Interpolation (Sec. 2.2): vel[k] = sum over the 27 stencil nodes of
+ * w_kn field[leaf(n)].  field: (n_leaves, 3) in leaf-id order. */
+int ot_interpolate(const ot_tree *tree, const void *field, const void *pos, int32_t dtype,
+                   int64_t n, void *vel, void *stream);
+
+/* Spreading (Sec. 2.2): field_out[j] (+)= sum_k sum_{n: leaf(n) = j} w_kn
+ * force[k], the exact transpose of ot_interpolate.  accumulate = 0 overwrites
+ * field_out, 1 adds to it.  mode: OT_SPREAD_ATOMIC or OT_SPREAD_FIXED.  Uses
+ * the tree's workspace in FIXED mode: FIXED calls on one tree must not run
+ * concurrently on different streams. */
+int ot_spread(const ot_tree *tree, const void *force, const void *pos, int32_t dtype, int64_t n,
+              int32_t mode, int32_t accumulate, void *field_out, void *stream);
+
+/* One fused pass over the points: host search, interpolation of `field`
+ * and spreading of `force` share the stencil.  ops: OT_OP_* bits; ids,
+ * vel, force/field_out may be NULL when their op is off.  field_out is
+ * overwritten (accumulate = 0) or added to (1). */
+int ot_track(const ot_tree *tree, int32_t ops, const void *field, const void *force,
+             const void *pos, int32_t dtype, int64_t n, int32_t mode, int32_t accumulate,
+             int32_t *ids, void *vel, void *field_out, void *stream);
+
+/* Position gradient through the delta-function derivative:
+ * grad[k, d] = sum_n (vec[k] . field[leaf(n)]) dw_kn/dX_d with
+ * dw/dX_d = 2^l phi'(r_d) prod_{e != d} phi(r_e), the host leaf held fixed.
+ * With field = interpolated field and vec = dLoss/dvel this is the gradient
+ * of interpolate; with field = dLoss/dfield_out and vec = force it is the
+ * gradient of spread.  grad: (n, 3). */
+int ot_grad_pos(const ot_tree *tree, const void *field, const void *vec, const void *pos,
+                int32_t dtype, int64_t n, void *grad, void *stream);
+
+/* Batched pass over many point sets of uneven size (bubbles' markers and
+ * particle groups) in one persistent launch captured in a HIP graph.
+ * offsets: host (n_inst + 1,) int64, ascending, offsets[0] = 0; instance i
+ * owns points [offsets[i], offsets[i+1]).  ops: host (n_inst,) OT_OP_* bits
+ * per instance.  Tiles of <= tuning.tile points never straddle instances.
+ * The plan copies offsets/ops; it keeps the tree pointer (destroy the plan
+ * before the tree). */
+int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets, const int32_t *ops,
+                         int32_t n_inst, int32_t dtype, int32_t mode, const ot_tuning *tuning,
+                         ot_batch_plan **out);
+
+/* Run a plan: like ot_track over all instances (field_out overwritten).
+ * The first run with a given set of pointers and stream captures a graph;
+ * later runs with the same set replay it. */
+int ot_batch_run(ot_batch_plan *plan, const void *field, const void *force, const void *pos,
+                 int32_t *ids, void *vel, void *field_out, void *stream);
+
+/* Timing of the persistent kernel: with enable = 1 the plan records a pair
+ * of HIP events just before and after its persistent kernel inside the
+ * graph (on the stream the graph runs on); ot_batch_last_kernel_ms returns
+ * the kernel's duration in the last completed run (OT_ERR_HIP while that run
+ * is still in flight).  Changing the setting re-captures the graph. */
+int ot_batch_plan_timing(ot_batch_plan *plan, int32_t enable);
+int ot_batch_last_kernel_ms(const ot_batch_plan *plan, float *ms);
+
+/* Tiles and workgroups a plan uses (host ints, either may be NULL). */
+int ot_batch_plan_shape(const ot_batch_plan *plan, int64_t *n_tiles, int32_t *grid);
+
+int ot_batch_plan_destroy(ot_batch_plan *plan);
+
+/* Static message for an error code; message of this thread's last error. */
+const char *ot_strerror(int32_t code);
+const char *ot_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OCTRACK_H */

@@ -1,0 +1,340 @@
+"""MI355X (gfx950) Lagrangian-point tracking on adaptive octrees.
+
+Thin ctypes binding of ``libocttrack.so`` (declared in ``include/octrack.h``):
+host-cell search (Algorithm 1 semantics), 3-point regularized-delta
+interpolation and force spreading (Sec. 2.2), their position gradient, and a
+batched persistent pass.  Torch tensors provide device memory and streams;
+every step of the computation runs in the library's HIP kernels.  There is
+no CPU fallback: importing this package fails if the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libocttrack.so")
+
+OT_OK = 0
+OT_F32, OT_F64 = 0, 1
+OT_SPREAD_ATOMIC, OT_SPREAD_FIXED = 0, 1
+OT_OP_LOCATE, OT_OP_INTERPOLATE, OT_OP_SPREAD = 1, 2, 4
+
+ERRORS = {-1: "OT_ERR_INVALID", -2: "OT_ERR_NOT_PARTITION", -3: "OT_ERR_UNSORTED_DUP",
+          -4: "OT_ERR_LEVEL_RANGE", -5: "OT_ERR_OOM", -6: "OT_ERR_HIP", -7: "OT_ERR_CAPACITY"}
+
+
+class OtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+class TreeDesc(ctypes.Structure):
+    _fields_ = [("l_min", ctypes.c_int32), ("l_max", ctypes.c_int32), ("periodic", ctypes.c_int32)]
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("n_leaves", ctypes.c_int64), ("l_min", ctypes.c_int32), ("l_max", ctypes.c_int32),
+                ("periodic", ctypes.c_int32), ("table_levels", ctypes.c_int32),
+                ("table_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("tile", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_get", "ot_tree_leaves",
+           "ot_locate", "ot_interpolate", "ot_spread", "ot_track", "ot_grad_pos", "ot_batch_plan_create",
+           "ot_batch_run", "ot_batch_plan_shape", "ot_batch_plan_timing", "ot_batch_last_kernel_ms",
+           "ot_batch_plan_destroy", "ot_strerror", "ot_last_error")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2605_20565_amd.build` "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sigs = {
+        "ot_encode_keys": [P, i64, i32, P, P],
+        "ot_build_tree": [P, P, i64, ctypes.POINTER(TreeDesc), P, P, ctypes.POINTER(P)],
+        "ot_destroy_tree": [P],
+        "ot_tree_info_get": [P, ctypes.POINTER(TreeInfo)],
+        "ot_tree_leaves": [P, P, P, P],
+        "ot_locate": [P, P, i32, i64, P, P],
+        "ot_interpolate": [P, P, P, i32, i64, P, P],
+        "ot_spread": [P, P, P, i32, i64, i32, i32, P, P],
+        "ot_track": [P, i32, P, P, P, i32, i64, i32, i32, P, P, P, P],
+        "ot_grad_pos": [P, P, P, P, i32, i64, P, P],
+        "ot_batch_plan_create": [P, P, P, i32, i32, i32, ctypes.POINTER(Tuning), ctypes.POINTER(P)],
+        "ot_batch_run": [P, P, P, P, P, P, P, P],
+        "ot_batch_plan_shape": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
+        "ot_batch_plan_timing": [P, i32],
+        "ot_batch_last_kernel_ms": [P, ctypes.POINTER(ctypes.c_float)],
+        "ot_batch_plan_destroy": [P],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.ot_strerror.argtypes = [i32]
+    L.ot_strerror.restype = ctypes.c_char_p
+    L.ot_last_error.argtypes = []
+    L.ot_last_error.restype = ctypes.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int) -> None:
+    if rc != OT_OK:
+        raise OtError(rc, lib.ot_last_error().decode())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return OT_F32
+    if t.dtype == torch.float64:
+        return OT_F64
+    raise TypeError(f"positions/fields must be float32 or float64, got {t.dtype}")
+
+
+def _rows3(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dim() != 2 or t.shape[1] != 3:
+        raise ValueError(f"{name} must have shape (n, 3)")
+    return t.contiguous()
+
+
+def _check_out(t: Optional[torch.Tensor], rows: int, dtype, device, name: str) -> None:
+    if t is None:
+        return
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() < rows * (3 if t.dim() == 2 else 1):
+        raise ValueError(f"{name}: needs a contiguous {dtype} device tensor with {rows} rows")
+
+
+def _mode_code(mode) -> int:
+    if mode in ("atomic", OT_SPREAD_ATOMIC):
+        return OT_SPREAD_ATOMIC
+    if mode in ("fixed", OT_SPREAD_FIXED):
+        return OT_SPREAD_FIXED
+    raise ValueError(f"unknown spread mode {mode!r}")
+
+
+def encode_keys(anchors: torch.Tensor, l_max: int) -> torch.Tensor:
+    """Morton keys (returned as int64 bit patterns) of (n, 3) uint32/int32 anchors."""
+    a = anchors.contiguous()
+    if a.dtype not in (torch.int32, torch.uint32):
+        raise TypeError("anchors must be int32/uint32")
+    keys = torch.empty(a.shape[0], dtype=torch.int64, device=a.device)
+    _check(lib.ot_encode_keys(_ptr(a), a.shape[0], l_max, _ptr(keys), _stream()))
+    return keys
+
+
+class Tree:
+    """A built octree on the current device (see ``ot_build_tree``).
+
+    ``perm[id]`` is the input row of the leaf with Morton rank ``id``.
+    """
+
+    def __init__(self, keys: torch.Tensor, levels: torch.Tensor, l_min: int, l_max: int, periodic: bool = True):
+        keys = keys.contiguous()
+        levels = levels.contiguous()
+        if keys.dtype not in (torch.int64, torch.uint64) or levels.dtype != torch.uint8:
+            raise TypeError("keys must be int64/uint64 and levels uint8")
+        n = keys.shape[0]
+        self.perm = torch.empty(n, dtype=torch.int32, device=keys.device)
+        desc = TreeDesc(l_min, l_max, 1 if periodic else 0)
+        h = ctypes.c_void_p()
+        _check(lib.ot_build_tree(_ptr(keys), _ptr(levels), n, ctypes.byref(desc), _ptr(self.perm), _stream(),
+                                 ctypes.byref(h)))
+        self._h = h
+        self.l_min, self.l_max, self.periodic = int(l_min), int(l_max), bool(periodic)
+        self.n_leaves = int(n)
+        self.device = keys.device
+
+    @classmethod
+    def from_anchors(cls, anchors: torch.Tensor, levels: torch.Tensor, l_min: int, l_max: int,
+                     periodic: bool = True) -> "Tree":
+        return cls(encode_keys(anchors, l_max), levels, l_min, l_max, periodic)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib.ot_destroy_tree(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> TreeInfo:
+        inf = TreeInfo()
+        _check(lib.ot_tree_info_get(self._h, ctypes.byref(inf)))
+        return inf
+
+    def leaves(self) -> Tuple[torch.Tensor, torch.Tensor]:
+        k = torch.empty(self.n_leaves, dtype=torch.int64, device=self.device)
+        lv = torch.empty(self.n_leaves, dtype=torch.uint8, device=self.device)
+        _check(lib.ot_tree_leaves(self._h, _ptr(k), _ptr(lv), _stream()))
+        return k, lv
+
+    def permute_rows(self, rows: torch.Tensor) -> torch.Tensor:
+        """Rows in the caller's leaf order -> leaf-id (Morton) order."""
+        return rows.index_select(0, self.perm.long()).contiguous()
+
+    # -- the tracking step -------------------------------------------------
+    def locate(self, pos: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        pos = _rows3(pos, "pos")
+        _check_out(out, pos.shape[0], torch.int32, pos.device, "out")
+        ids = out if out is not None else torch.empty(pos.shape[0], dtype=torch.int32, device=pos.device)
+        _check(lib.ot_locate(self._h, _ptr(pos), _dtype_code(pos), pos.shape[0], _ptr(ids), _stream()))
+        return ids
+
+    def interpolate(self, field: torch.Tensor, pos: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        pos = _rows3(pos, "pos")
+        field = _rows3(field, "field")
+        if field.dtype != pos.dtype or field.shape[0] != self.n_leaves:
+            raise ValueError("field must be (n_leaves, 3) with the dtype of pos")
+        _check_out(out, pos.shape[0], pos.dtype, pos.device, "out")
+        vel = out if out is not None else torch.empty_like(pos)
+        _check(lib.ot_interpolate(self._h, _ptr(field), _ptr(pos), _dtype_code(pos), pos.shape[0], _ptr(vel),
+                                  _stream()))
+        return vel
+
+    def spread(self, force: torch.Tensor, pos: torch.Tensor, mode="atomic", out: Optional[torch.Tensor] = None,
+               accumulate: bool = False) -> torch.Tensor:
+        pos = _rows3(pos, "pos")
+        force = _rows3(force, "force")
+        if force.dtype != pos.dtype or force.shape[0] != pos.shape[0]:
+            raise ValueError("force must be (n, 3) with the dtype of pos")
+        if out is None:
+            out = torch.empty((self.n_leaves, 3), dtype=pos.dtype, device=pos.device)
+            accumulate = False
+        _check_out(out, self.n_leaves, pos.dtype, pos.device, "out")
+        _check(lib.ot_spread(self._h, _ptr(force), _ptr(pos), _dtype_code(pos), pos.shape[0], _mode_code(mode),
+                             1 if accumulate else 0, _ptr(out), _stream()))
+        return out
+
+    def track(self, pos: torch.Tensor, field: Optional[torch.Tensor] = None, force: Optional[torch.Tensor] = None,
+              ops: int = OT_OP_LOCATE | OT_OP_INTERPOLATE | OT_OP_SPREAD, mode="atomic",
+              ids: Optional[torch.Tensor] = None, vel: Optional[torch.Tensor] = None,
+              field_out: Optional[torch.Tensor] = None, accumulate: bool = False):
+        """Fused pass: returns (ids, vel, field_out) (None where the op is off)."""
+        pos = _rows3(pos, "pos")
+        n = pos.shape[0]
+        if ops & OT_OP_LOCATE and ids is None:
+            ids = torch.empty(n, dtype=torch.int32, device=pos.device)
+        if ops & OT_OP_INTERPOLATE and vel is None:
+            vel = torch.empty_like(pos)
+        if ops & OT_OP_SPREAD and field_out is None:
+            field_out = torch.empty((self.n_leaves, 3), dtype=pos.dtype, device=pos.device)
+            accumulate = False
+        if field is not None:
+            field = _rows3(field, "field")
+            if field.shape[0] != self.n_leaves or field.dtype != pos.dtype:
+                raise ValueError("field must be (n_leaves, 3) with the dtype of pos")
+        if force is not None:
+            force = _rows3(force, "force")
+            if force.shape[0] != n or force.dtype != pos.dtype:
+                raise ValueError("force must be (n, 3) with the dtype of pos")
+        _check_out(ids, n, torch.int32, pos.device, "ids")
+        _check_out(vel, n, pos.dtype, pos.device, "vel")
+        _check_out(field_out, self.n_leaves, pos.dtype, pos.device, "field_out")
+        _check(lib.ot_track(self._h, ops, _ptr(field), _ptr(force), _ptr(pos), _dtype_code(pos), n,
+                            _mode_code(mode), 1 if accumulate else 0, _ptr(ids), _ptr(vel), _ptr(field_out),
+                            _stream()))
+        return ids, vel, field_out
+
+    def grad_pos(self, field: torch.Tensor, vec: torch.Tensor, pos: torch.Tensor,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        pos = _rows3(pos, "pos")
+        field = _rows3(field, "field")
+        vec = _rows3(vec, "vec")
+        if field.shape[0] != self.n_leaves or vec.shape[0] != pos.shape[0]:
+            raise ValueError("field must be (n_leaves, 3) and vec (n, 3)")
+        if field.dtype != pos.dtype or vec.dtype != pos.dtype:
+            raise ValueError("field, vec and pos must share a dtype")
+        _check_out(out, pos.shape[0], pos.dtype, pos.device, "out")
+        g = out if out is not None else torch.empty_like(pos)
+        _check(lib.ot_grad_pos(self._h, _ptr(field), _ptr(vec), _ptr(pos), _dtype_code(pos), pos.shape[0],
+                               _ptr(g), _stream()))
+        return g
+
+
+class BatchPlan:
+    """Many point sets in one persistent, graph-replayed pass (``ot_batch_*``)."""
+
+    def __init__(self, tree: Tree, offsets: Sequence[int], ops: Sequence[int], dtype=torch.float32,
+                 mode="atomic", block: int = 0, tile: int = 0, grid: int = 0):
+        off = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
+        opa = (ctypes.c_int32 * len(ops))(*[int(v) for v in ops])
+        tun = Tuning(block, tile, grid, 0)
+        h = ctypes.c_void_p()
+        code = OT_F32 if dtype == torch.float32 else OT_F64
+        _check(lib.ot_batch_plan_create(tree.handle, off, opa, len(ops), code, _mode_code(mode), ctypes.byref(tun),
+                                        ctypes.byref(h)))
+        self._h = h
+        self.tree = tree
+        self.n_points = int(offsets[-1])
+        self.dtype = dtype
+
+    def shape(self) -> Tuple[int, int]:
+        nt, g = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib.ot_batch_plan_shape(self._h, ctypes.byref(nt), ctypes.byref(g)))
+        return nt.value, g.value
+
+    def set_timing(self, enable: bool) -> None:
+        _check(lib.ot_batch_plan_timing(self._h, 1 if enable else 0))
+
+    def last_kernel_ms(self) -> float:
+        v = ctypes.c_float()
+        _check(lib.ot_batch_last_kernel_ms(self._h, ctypes.byref(v)))
+        return float(v.value)
+
+    def run(self, pos, field=None, force=None, ids=None, vel=None, field_out=None):
+        n, nl = self.n_points, self.tree.n_leaves
+        _check_out(pos, n, self.dtype, None, "pos")
+        _check_out(force, n, self.dtype, None, "force")
+        _check_out(field, nl, self.dtype, None, "field")
+        _check_out(field_out, nl, self.dtype, None, "field_out")
+        _check_out(vel, n, self.dtype, None, "vel")
+        _check_out(ids, n, torch.int32, None, "ids")
+        _check(lib.ot_batch_run(self._h, _ptr(field), _ptr(force), _ptr(pos), _ptr(ids), _ptr(vel),
+                                _ptr(field_out), _stream()))
+        return ids, vel, field_out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ot_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+from .autograd import InterpolateFn, SpreadFn, interpolate, spread  # noqa: E402,F401

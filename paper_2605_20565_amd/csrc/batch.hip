@@ -1,0 +1,275 @@
+// Batched tracking of many point sets of uneven size in one persistent
+// launch.  The paper's bubble/particle workloads mix a few hundred bubbles
+// with 10^2..10^4 markers each and particle groups of 10^4..10^6 points
+// (bubble-driven load imbalance, Sec. 5.2); launching one kernel per set
+// leaves the chip idle on the small ones.  Here the sets are cut into tiles
+// that never straddle a set, a fixed grid of workgroups pulls tiles from a
+// device counter until none are left, and the whole sequence (clears,
+// fixed-point scale, persistent kernel, finalize) is captured once in a HIP
+// graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "ot_common.h"
+#include "track_device.h"
+
+namespace ot {
+int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const void *force, int64_t n, void *fout,
+                    hipStream_t s);
+int spread_epilogue(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
+}  // namespace ot
+
+struct ot_batch_plan {
+    const ot_tree *tree;
+    int dtype, mode;
+    int block, tile, grid;
+    int ops_union;
+    int64_t n_points, n_tiles;
+    int64_t *tile_start;      // device
+    uint32_t *tile_info;      // device: count | ops << 24
+    unsigned *counter;        // device
+    hipStream_t capture_stream;
+    bool have_graph;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    const void *key[6];
+    bool timing;              // record ev[0]/ev[1] around the persistent kernel
+    hipEvent_t ev[2];
+};
+
+namespace ot {
+namespace {
+
+constexpr uint32_t kCountMask = 0x00FFFFFFu;
+
+template <typename T, int MODE>
+__global__ void k_batch(TreeView tv, const int64_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_info,
+                        int64_t n_tiles, unsigned *__restrict__ counter, const T *__restrict__ pos,
+                        const T *__restrict__ field, const T *__restrict__ force, int32_t *__restrict__ ids,
+                        T *__restrict__ vel, T *__restrict__ fout, unsigned long long *__restrict__ facc,
+                        const FxState *__restrict__ fx)
+{
+    __shared__ unsigned s_tile;
+    const double scale = MODE == kModeFixed ? fx->scale : 0.0;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        __syncthreads();
+        if (tile >= n_tiles) break;   // same value in every thread of the workgroup
+        const int64_t start = tile_start[tile];
+        const uint32_t info = tile_info[tile];
+        const int cnt = (int)(info & kCountMask);
+        const int ops = (int)(info >> 24);
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+            const int64_t k = start + i;
+            switch (ops) {
+#define OT_CASE(OPSV) \
+    case OPSV: track_point<T, OPSV, MODE>(tv, k, pos, field, force, ids, vel, fout, facc, scale); break;
+                OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
+#undef OT_CASE
+            default: break;
+            }
+        }
+    }
+}
+
+template <typename T, int MODE>
+int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids, void *vel,
+            void *fout, hipStream_t s)
+{
+    const ot_tree *t = p->tree;
+    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, p->counter, (int64_t)1, 0u);
+    int rc;
+    if (p->ops_union & kOpSpread)
+        if ((rc = spread_prologue(t, p->dtype, p->mode, 0, force, p->n_points, fout, s))) return rc;
+    if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
+    hipLaunchKernelGGL((k_batch<T, MODE>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start, p->tile_info,
+                       p->n_tiles, p->counter, (const T *)pos, (const T *)field, (const T *)force, ids, (T *)vel,
+                       (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+    OT_HIP(hipGetLastError());
+    if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
+    if (p->ops_union & kOpSpread)
+        if ((rc = spread_epilogue(t, p->dtype, p->mode, 0, fout, s))) return rc;
+    return OT_OK;
+}
+
+int enqueue_any(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids, void *vel,
+                void *fout, hipStream_t s)
+{
+    if (p->dtype == OT_F32)
+        return p->mode == OT_SPREAD_FIXED ? enqueue<float, kModeFixed>(p, field, force, pos, ids, vel, fout, s)
+                                          : enqueue<float, kModeAtomic>(p, field, force, pos, ids, vel, fout, s);
+    return p->mode == OT_SPREAD_FIXED ? enqueue<double, kModeFixed>(p, field, force, pos, ids, vel, fout, s)
+                                      : enqueue<double, kModeAtomic>(p, field, force, pos, ids, vel, fout, s);
+}
+
+void drop_graph(ot_batch_plan *p)
+{
+    if (p->have_graph) {
+        (void)hipGraphExecDestroy(p->exec);
+        (void)hipGraphDestroy(p->graph);
+        p->have_graph = false;
+    }
+}
+
+}  // namespace
+}  // namespace ot
+
+using namespace ot;
+
+extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets, const int32_t *ops, int32_t n_inst,
+                                    int32_t dtype, int32_t mode, const ot_tuning *tuning, ot_batch_plan **out)
+{
+    if (!out) return fail(OT_ERR_INVALID, "ot_batch_plan_create: out is NULL");
+    *out = nullptr;
+    if (!tree || !offsets || !ops || n_inst <= 0) return fail(OT_ERR_INVALID, "ot_batch_plan_create: bad arguments");
+    if (dtype != OT_F32 && dtype != OT_F64) return fail(OT_ERR_INVALID, "dtype must be OT_F32 or OT_F64");
+    if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
+    int block = tuning && tuning->block ? tuning->block : 256;
+    int tile = tuning && tuning->tile ? tuning->tile : 4 * block;
+    if (block < 64 || block > 1024 || block % 64) return fail(OT_ERR_INVALID, "block must be a multiple of 64 in [64, 1024]");
+    if (tile < block || tile % block || tile > (int)kCountMask) return fail(OT_ERR_INVALID, "tile must be a multiple of block");
+    if (offsets[0] != 0) return fail(OT_ERR_INVALID, "offsets[0] must be 0");
+    std::vector<int64_t> starts;
+    std::vector<uint32_t> infos;
+    int ops_union = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        if (offsets[i + 1] < offsets[i]) return fail(OT_ERR_INVALID, "offsets must be ascending");
+        if (ops[i] < 0 || ops[i] > 7) return fail(OT_ERR_INVALID, "bad per-instance ops");
+        if (ops[i] == 0) continue;
+        ops_union |= ops[i];
+        for (int64_t a = offsets[i]; a < offsets[i + 1]; a += tile) {
+            const int64_t c = std::min<int64_t>(tile, offsets[i + 1] - a);
+            starts.push_back(a);
+            infos.push_back((uint32_t)c | ((uint32_t)ops[i] << 24));
+        }
+    }
+    ot_batch_plan *p = new ot_batch_plan();
+    p->tree = tree;
+    p->dtype = dtype;
+    p->mode = mode;
+    p->block = block;
+    p->tile = tile;
+    p->ops_union = ops_union;
+    p->n_points = offsets[n_inst];
+    p->n_tiles = (int64_t)starts.size();
+    p->have_graph = false;
+    int cus = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int per_cu = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch<float, kModeAtomic>, block, 0);
+    if (per_cu <= 0) per_cu = 1;
+    int grid = tuning && tuning->grid ? tuning->grid : std::max(1, cus) * per_cu;
+    if (p->n_tiles > 0 && grid > p->n_tiles) grid = (int)p->n_tiles;
+    p->grid = std::max(1, grid);
+    hipError_t e1 = hipMalloc((void **)&p->tile_start, std::max<size_t>(8, starts.size() * 8));
+    hipError_t e2 = hipMalloc((void **)&p->tile_info, std::max<size_t>(4, infos.size() * 4));
+    hipError_t e3 = hipMalloc((void **)&p->counter, 64);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        (void)hipGetLastError();
+        ot_batch_plan_destroy(p);
+        return fail(OT_ERR_OOM, "ot_batch_plan_create: device allocation failed");
+    }
+    if (!starts.empty()) {
+        hipError_t e = hipMemcpy(p->tile_start, starts.data(), starts.size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(p->tile_info, infos.data(), infos.size() * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            ot_batch_plan_destroy(p);
+            return hip_fail(e, "ot_batch_plan_create: upload");
+        }
+    }
+    hipError_t e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        p->capture_stream = nullptr;
+        ot_batch_plan_destroy(p);
+        return hip_fail(e, "ot_batch_plan_create: stream");
+    }
+    *out = p;
+    return OT_OK;
+}
+
+extern "C" int ot_batch_run(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids,
+                            void *vel, void *field_out, void *stream)
+{
+    if (!p) return fail(OT_ERR_INVALID, "plan is NULL");
+    const int u = p->ops_union;
+    if (p->n_points > 0 && !pos) return fail(OT_ERR_INVALID, "pos is NULL");
+    if ((u & kOpLocate) && !ids) return fail(OT_ERR_INVALID, "ids is NULL");
+    if ((u & kOpInterp) && (!field || !vel)) return fail(OT_ERR_INVALID, "field or vel is NULL");
+    if ((u & kOpSpread) && (!force || !field_out)) return fail(OT_ERR_INVALID, "force or field_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const void *key[6] = {field, force, pos, ids, vel, field_out};
+    if (!p->have_graph || std::memcmp(key, p->key, sizeof(key)) != 0) {
+        drop_graph(p);
+        OT_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_any(p, field, force, pos, ids, vel, field_out, p->capture_stream);
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(p->capture_stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ec != hipSuccess) return hip_fail(ec, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(ei, "hipGraphInstantiate");
+        }
+        p->graph = g;
+        p->exec = ex;
+        p->have_graph = true;
+        std::memcpy(p->key, key, sizeof(key));
+    }
+    OT_HIP(hipGraphLaunch(p->exec, s));
+    return OT_OK;
+}
+
+extern "C" int ot_batch_plan_shape(const ot_batch_plan *p, int64_t *n_tiles, int32_t *grid)
+{
+    if (!p) return fail(OT_ERR_INVALID, "plan is NULL");
+    if (n_tiles) *n_tiles = p->n_tiles;
+    if (grid) *grid = p->grid;
+    return OT_OK;
+}
+
+extern "C" int ot_batch_plan_timing(ot_batch_plan *p, int32_t enable)
+{
+    if (!p) return fail(OT_ERR_INVALID, "plan is NULL");
+    const bool on = enable != 0;
+    if (on == p->timing) return OT_OK;
+    drop_graph(p);
+    if (on && !p->ev[0]) {
+        OT_HIP(hipEventCreate(&p->ev[0]));
+        OT_HIP(hipEventCreate(&p->ev[1]));
+    }
+    p->timing = on;
+    return OT_OK;
+}
+
+extern "C" int ot_batch_last_kernel_ms(const ot_batch_plan *p, float *ms)
+{
+    if (!p || !ms) return fail(OT_ERR_INVALID, "NULL argument");
+    if (!p->timing) return fail(OT_ERR_INVALID, "timing is off for this plan");
+    OT_HIP(hipEventElapsedTime(ms, p->ev[0], p->ev[1]));
+    return OT_OK;
+}
+
+extern "C" int ot_batch_plan_destroy(ot_batch_plan *p)
+{
+    if (!p) return OT_OK;
+    (void)hipDeviceSynchronize();
+    drop_graph(p);
+    if (p->ev[0]) (void)hipEventDestroy(p->ev[0]);
+    if (p->ev[1]) (void)hipEventDestroy(p->ev[1]);
+    if (p->tile_start) (void)hipFree(p->tile_start);
+    if (p->tile_info) (void)hipFree(p->tile_info);
+    if (p->counter) (void)hipFree(p->counter);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    delete p;
+    return OT_OK;
+}

@@ -1,0 +1,158 @@
+// Internal definitions shared by the library's HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/octrack.h"
+
+namespace ot {
+
+// ---------------------------------------------------------------------------
+// Descent table.
+//
+// The Z-sorted leaf array (Sec. 3.1) is searched through a radix table over
+// Morton digits instead of per-level binary searches: the root holds one
+// entry per cell of level r = min(l_min, 8); a cell that is split into finer
+// leaves points to a sub-table holding the cells up to 3 levels deeper
+// (512 entries), and so on down to L.  Every entry is either
+//   LEAF : bit 31 = 0, bits 26..30 = leaf level, bits 0..25 = leaf id
+//   SPLIT: bit 31 = 1, bits 0..30 = sub-table index at the next table level.
+// A lookup costs one dependent load per table level (2 for trees that span
+// at most 3 levels below the root), and returns the leaf and its level at
+// once.  It returns the same leaf as Algorithm 1 for every point: both find
+// the unique leaf whose half-open box contains the point.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSplit = 0x80000000u;
+constexpr uint32_t kIdMask = 0x03FFFFFFu;
+constexpr int kLevelShift = 26;
+constexpr int kMaxTabLevels = 9;
+constexpr int kMaxRootLevel = 8;
+constexpr int64_t kMaxLeaves = int64_t(1) << 26;
+
+struct TreeView {
+    const uint32_t *table;
+    int32_t L;         // finest level
+    int32_t periodic;
+    int32_t nlev;      // table levels (root included)
+    int32_t pad;
+    int32_t lev[kMaxTabLevels];   // cell level of each table level; lev[0] = root level
+    int64_t off[kMaxTabLevels];   // entry offset of each level's pool; off[0] = 0
+};
+
+// Spread the low 10 bits of v so that bit b lands on bit 3b.
+__host__ __device__ __forceinline__ uint32_t part1by2(uint32_t v)
+{
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__host__ __device__ __forceinline__ uint32_t interleave3(uint32_t x, uint32_t y, uint32_t z)
+{
+    return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
+}
+
+// Table entry of the leaf containing the finest-level cell (ix, iy, iz).
+__device__ __forceinline__ uint32_t descend(const TreeView &tv, uint32_t ix, uint32_t iy,
+                                            uint32_t iz)
+{
+    int sh = tv.L - tv.lev[0];
+    uint32_t e = __ldg(tv.table + interleave3(ix >> sh, iy >> sh, iz >> sh));
+    for (int t = 1; t < tv.nlev && (e & kSplit); ++t) {
+        int d = tv.lev[t] - tv.lev[t - 1];
+        int s = tv.L - tv.lev[t];
+        uint32_t m = (1u << d) - 1u;
+        uint32_t sub = interleave3((ix >> s) & m, (iy >> s) & m, (iz >> s) & m);
+        e = __ldg(tv.table + tv.off[t] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
+    }
+    return e;
+}
+
+// Integer coordinates at level L: floor(x 2^L) in FP64, wrapped (periodic)
+// or range-checked.  False when the point has no host cell.
+template <typename T>
+__device__ __forceinline__ bool point_cell(const TreeView &tv, T x, T y, T z, uint32_t I[3])
+{
+    const double sc = (double)(int64_t(1) << tv.L);
+    const int64_t M = int64_t(1) << tv.L;
+    double v[3] = {(double)x * sc, (double)y * sc, (double)z * sc};
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ok = ok && (fabs(v[d]) < 4503599627370496.0);   // 2^52; false for NaN
+        int64_t c = ok ? (int64_t)floor(v[d]) : 0;
+        if (tv.periodic) {
+            c &= (M - 1);                                 // floor-mod for two's complement
+        } else {
+            ok = ok && (c >= 0) && (c < M);
+        }
+        I[d] = (uint32_t)c;
+    }
+    return ok;
+}
+
+// 1-D weights of the three stencil nodes i0-1, i0, i0+1 for a point at
+// fractional offset t in [0,1) inside its level-l cell.  With u = t - 1/2
+// the node distances are u+1, u, u-1 and all three branches of phi share
+// q = sqrt(1 - 3u^2):
+//   phi(u+1) = (2 - 3u - q)/6,  phi(u) = (1 + q)/3,  phi(u-1) = (2 + 3u - q)/6
+// (substituting |r| = 1+u, |u|, 1-u into the phi equation of Sec. 2.2;
+// -2 + 6|r| - 3r^2 = 1 - 3u^2 for |r| = 1 +- u).  Derivatives d/du:
+//   (-1 + u/q)/2,  -u/q,  (1 + u/q)/2.
+template <typename T>
+__device__ __forceinline__ void delta3(T t, T w[3])
+{
+    const T u = t - T(0.5);
+    const T q = sqrt(T(1) - T(3) * u * u);
+    w[0] = (T(2) - T(3) * u - q) * T(1.0 / 6.0);
+    w[1] = (T(1) + q) * T(1.0 / 3.0);
+    w[2] = (T(2) + T(3) * u - q) * T(1.0 / 6.0);
+}
+
+template <typename T>
+__device__ __forceinline__ void delta3_grad(T t, T w[3], T dw[3])
+{
+    const T u = t - T(0.5);
+    const T q = sqrt(T(1) - T(3) * u * u);
+    const T uq = u / q;
+    w[0] = (T(2) - T(3) * u - q) * T(1.0 / 6.0);
+    w[1] = (T(1) + q) * T(1.0 / 3.0);
+    w[2] = (T(2) + T(3) * u - q) * T(1.0 / 6.0);
+    dw[0] = (uq - T(1)) * T(0.5);
+    dw[1] = -uq;
+    dw[2] = (uq + T(1)) * T(0.5);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define OT_HIP(call)                                      \
+    do {                                                  \
+        hipError_t _e = (call);                           \
+        if (_e != hipSuccess) return ot::hip_fail(_e, #call); \
+    } while (0)
+
+}  // namespace ot
+
+struct ot_tree {
+    int device;
+    int32_t l_min, l_max, periodic;
+    int64_t n_leaves;
+    uint64_t *keys;      // sorted Morton keys
+    uint8_t *levels;     // levels in sorted order
+    uint32_t *table;     // descent table (root + pools)
+    int64_t table_entries;
+    ot::TreeView view;
+    unsigned long long *fx_acc;   // fixed-point accumulators, n_leaves * 3
+    unsigned int *scratch;        // small device scratch (reductions)
+};

@@ -1,0 +1,198 @@
+// Host-cell search, interpolation, spreading and the position gradient.
+//
+// One thread per Lagrangian point.  A point's integer cell is floor(x 2^L)
+// in FP64 (so that a face decision never flips between precisions), its host
+// leaf comes from the descent table (Sec. 3.2 / Algorithm 1 semantics), and
+// the 3x3x3 stencil at the host level uses the 3-point delta function of
+// Sec. 2.2.  Interpolation gathers the 27 node values; spreading scatters
+// w F to the same 27 node leaves (atomics in the working precision, or
+// int64 fixed point for order-independent sums).
+#include <hip/hip_runtime.h>
+
+#include "ot_common.h"
+#include "track_device.h"
+
+namespace ot {
+
+namespace {
+
+template <typename T, int OPS, int MODE>
+__global__ __launch_bounds__(256) void k_track(TreeView tv, int64_t n, const T *__restrict__ pos,
+                                               const T *__restrict__ field, const T *__restrict__ force,
+                                               int32_t *__restrict__ ids, T *__restrict__ vel,
+                                               T *__restrict__ fout, unsigned long long *__restrict__ facc,
+                                               const FxState *__restrict__ fx)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double scale = (OPS & kOpSpread) && MODE == kModeFixed ? fx->scale : 0.0;
+    track_point<T, OPS, MODE>(tv, k, pos, field, force, ids, vel, fout, facc, scale);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad(TreeView tv, int64_t n, const T *__restrict__ pos,
+                                              const T *__restrict__ field, const T *__restrict__ vec,
+                                              T *__restrict__ grad)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    grad_point<T>(tv, k, pos, field, vec, grad);
+}
+
+template <typename T, int MODE>
+int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, hipStream_t s, int64_t n, const void *pos,
+                 const void *field, const void *force, int32_t *ids, void *vel, void *fout)
+{
+    const T *P = (const T *)pos, *Fd = (const T *)field, *Fo = (const T *)force;
+    T *V = (T *)vel, *O = (T *)fout;
+    const FxState *fx = (const FxState *)t->scratch;
+#define OT_LAUNCH(OPSV)                                                                                  \
+    hipLaunchKernelGGL((k_track<T, OPSV, MODE>), g, b, 0, s, t->view, n, P, Fd, Fo, ids, V, O, t->fx_acc, fx); \
+    break;
+    switch (ops) {
+    case 1: OT_LAUNCH(1)
+    case 2: OT_LAUNCH(2)
+    case 3: OT_LAUNCH(3)
+    case 4: OT_LAUNCH(4)
+    case 5: OT_LAUNCH(5)
+    case 6: OT_LAUNCH(6)
+    case 7: OT_LAUNCH(7)
+    default: return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
+    }
+#undef OT_LAUNCH
+    return OT_OK;
+}
+
+}  // namespace
+
+// Prepare the spreading target before a pass: zero the output (atomic mode,
+// overwrite) or the fixed-point accumulators and compute the scale.
+int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const void *force, int64_t n,
+                    void *fout, hipStream_t s)
+{
+    const int64_t n3 = t->n_leaves * 3;
+    FxState *fx = (FxState *)t->scratch;
+    if (mode == OT_SPREAD_ATOMIC) {
+        if (!accumulate) {
+            if (dtype == OT_F32) hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, (float *)fout, n3, 0.0f);
+            else hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, (double *)fout, n3, 0.0);
+        }
+    } else {
+        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1024), dim3(256), 0, s, t->fx_acc, n3, 0ull);
+        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &fx->maxbits, (int64_t)1, 0ull);
+        const int64_t m = n * 3;
+        if (m > 0) {
+            unsigned gb = (unsigned)std::min<int64_t>((m + 255) / 256, 2048);
+            if (dtype == OT_F32)
+                hipLaunchKernelGGL(k_maxabs<float>, dim3(gb), dim3(256), 0, s, (const float *)force, m, &fx->maxbits);
+            else
+                hipLaunchKernelGGL(k_maxabs<double>, dim3(gb), dim3(256), 0, s, (const double *)force, m, &fx->maxbits);
+        }
+        if (dtype == OT_F32) hipLaunchKernelGGL(k_fx_prepare<float>, dim3(1), dim3(64), 0, s, fx, n);
+        else hipLaunchKernelGGL(k_fx_prepare<double>, dim3(1), dim3(64), 0, s, fx, n);
+    }
+    OT_HIP(hipGetLastError());
+    return OT_OK;
+}
+
+int spread_epilogue(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s)
+{
+    if (mode != OT_SPREAD_FIXED) return OT_OK;
+    const int64_t n3 = t->n_leaves * 3;
+    const FxState *fx = (const FxState *)t->scratch;
+    const unsigned gb = (unsigned)std::min<int64_t>((n3 + 255) / 256, 8192);
+    if (dtype == OT_F32)
+        hipLaunchKernelGGL(k_fx_finalize<float>, dim3(gb), dim3(256), 0, s, t->fx_acc, (float *)fout, n3, fx, accumulate);
+    else
+        hipLaunchKernelGGL(k_fx_finalize<double>, dim3(gb), dim3(256), 0, s, t->fx_acc, (double *)fout, n3, fx, accumulate);
+    OT_HIP(hipGetLastError());
+    return OT_OK;
+}
+
+int check_common(const ot_tree *t, int dtype, int64_t n, const void *pos)
+{
+    if (!t) return fail(OT_ERR_INVALID, "tree is NULL");
+    if (dtype != OT_F32 && dtype != OT_F64) return fail(OT_ERR_INVALID, "dtype must be OT_F32 or OT_F64");
+    if (n < 0) return fail(OT_ERR_INVALID, "n < 0");
+    if (n > 0 && !pos) return fail(OT_ERR_INVALID, "pos is NULL");
+    if (n > (int64_t(1) << 40)) return fail(OT_ERR_CAPACITY, "too many points");
+    return OT_OK;
+}
+
+int track(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
+          int mode, int accumulate, int32_t *ids, void *vel, void *fout, hipStream_t s)
+{
+    int rc = check_common(t, dtype, n, pos);
+    if (rc) return rc;
+    if (ops <= 0 || ops > 7) return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
+    if ((ops & kOpLocate) && n > 0 && !ids) return fail(OT_ERR_INVALID, "ids is NULL");
+    if ((ops & kOpInterp) && ((n > 0 && !vel) || !field)) return fail(OT_ERR_INVALID, "field or vel is NULL");
+    if (ops & kOpSpread) {
+        if ((n > 0 && !force) || !fout) return fail(OT_ERR_INVALID, "force or field_out is NULL");
+        if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
+        if ((rc = spread_prologue(t, dtype, mode, accumulate, force, n, fout, s))) return rc;
+    }
+    if (n > 0) {
+        dim3 b(256), g((unsigned)((n + 255) / 256));
+        if (dtype == OT_F32)
+            rc = mode == OT_SPREAD_FIXED ? dispatch_ops<float, kModeFixed>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout)
+                                         : dispatch_ops<float, kModeAtomic>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout);
+        else
+            rc = mode == OT_SPREAD_FIXED ? dispatch_ops<double, kModeFixed>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout)
+                                         : dispatch_ops<double, kModeAtomic>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout);
+        if (rc) return rc;
+        OT_HIP(hipGetLastError());
+    }
+    if (ops & kOpSpread) return spread_epilogue(t, dtype, mode, accumulate, fout, s);
+    return OT_OK;
+}
+
+}  // namespace ot
+
+using namespace ot;
+
+extern "C" int ot_locate(const ot_tree *t, const void *pos, int32_t dtype, int64_t n, int32_t *ids, void *stream)
+{
+    return track(t, kOpLocate, nullptr, nullptr, pos, dtype, n, OT_SPREAD_ATOMIC, 0, ids, nullptr, nullptr,
+                 (hipStream_t)stream);
+}
+
+extern "C" int ot_interpolate(const ot_tree *t, const void *field, const void *pos, int32_t dtype, int64_t n,
+                              void *vel, void *stream)
+{
+    return track(t, kOpInterp, field, nullptr, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, vel, nullptr,
+                 (hipStream_t)stream);
+}
+
+extern "C" int ot_spread(const ot_tree *t, const void *force, const void *pos, int32_t dtype, int64_t n, int32_t mode,
+                         int32_t accumulate, void *field_out, void *stream)
+{
+    return track(t, kOpSpread, nullptr, force, pos, dtype, n, mode, accumulate, nullptr, nullptr, field_out,
+                 (hipStream_t)stream);
+}
+
+extern "C" int ot_track(const ot_tree *t, int32_t ops, const void *field, const void *force, const void *pos,
+                        int32_t dtype, int64_t n, int32_t mode, int32_t accumulate, int32_t *ids, void *vel,
+                        void *field_out, void *stream)
+{
+    return track(t, ops, field, force, pos, dtype, n, mode, accumulate, ids, vel, field_out, (hipStream_t)stream);
+}
+
+extern "C" int ot_grad_pos(const ot_tree *t, const void *field, const void *vec, const void *pos, int32_t dtype,
+                           int64_t n, void *grad, void *stream)
+{
+    int rc = check_common(t, dtype, n, pos);
+    if (rc) return rc;
+    if (n == 0) return OT_OK;
+    if (!field || !vec || !grad) return fail(OT_ERR_INVALID, "ot_grad_pos: NULL array");
+    dim3 b(256), g((unsigned)((n + 255) / 256));
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == OT_F32)
+        hipLaunchKernelGGL(k_grad<float>, g, b, 0, s, t->view, n, (const float *)pos, (const float *)field,
+                           (const float *)vec, (float *)grad);
+    else
+        hipLaunchKernelGGL(k_grad<double>, g, b, 0, s, t->view, n, (const double *)pos, (const double *)field,
+                           (const double *)vec, (double *)grad);
+    OT_HIP(hipGetLastError());
+    return OT_OK;
+}

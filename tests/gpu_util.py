@@ -1,0 +1,55 @@
+"""Helpers shared by the GPU parity tests: the same synthetic inputs go to the
+HIP library (through its C ABI binding) and to the FP64 oracle, and results
+are compared element by element with the metrics the tests state."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+import oracle
+import synth
+
+
+def gpu_tree(spec: synth.TreeSpec):
+    import paper_2605_20565_amd as ot
+    a = torch.from_numpy(spec.anchors.astype(np.int32)).cuda()
+    lv = torch.from_numpy(spec.levels).cuda()
+    return ot.Tree.from_anchors(a, lv, spec.l_min, spec.l_max, spec.periodic)
+
+
+def oracle_tree(spec: synth.TreeSpec) -> oracle.Tree:
+    return oracle.Tree.from_anchors(spec.anchors, spec.levels, spec.l_min, spec.l_max, spec.periodic)
+
+
+def as_dtype(x: np.ndarray, dtype) -> np.ndarray:
+    """Round inputs to the working precision; the oracle then sees exactly
+    what the GPU sees (promoted back to FP64)."""
+    return np.ascontiguousarray(x.astype(np.float32 if dtype == torch.float32 else np.float64).astype(np.float64))
+
+
+def to_dev(x: np.ndarray, dtype) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def scaled_err(got: np.ndarray, want: np.ndarray, scale: np.ndarray) -> float:
+    """max |got - want| / scale, the scale being the absolute stencil sum
+    (sum |w| |u| or sum |w F|): rounding in any order of the same sum stays
+    below (a few) ulp x scale."""
+    d = np.abs(np.asarray(got, dtype=np.float64) - want)
+    s = np.maximum(scale, 1e-300)
+    return float((d / s).max()) if d.size else 0.0
+
+
+def fixed_point_quantum(forces: np.ndarray) -> float:
+    """2^-s of the fixed-point spreading: s = 62 - E, 2^E >= n max|F|."""
+    n = forces.shape[0]
+    m = float(np.abs(forces[np.isfinite(forces)]).max()) if forces.size else 0.0
+    if m == 0.0 or n == 0:
+        return 1.0
+    _, E = math.frexp(n * m)
+    return math.ldexp(1.0, -(62 - E))
+
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}

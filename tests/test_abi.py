@@ -1,0 +1,61 @@
+"""The C ABI library loads and exports every symbol include/octrack.h
+declares; host-side argument checks answer without touching a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "octrack.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ot_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def ot():
+    import paper_2605_20565_amd as m
+    return m
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("ot_build_tree", "ot_locate", "ot_interpolate", "ot_spread", "ot_track", "ot_grad_pos",
+              "ot_batch_plan_create", "ot_batch_run", "ot_destroy_tree", "ot_strerror", "ot_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(ot):
+    out = subprocess.run(["nm", "-D", "--defined-only", ot.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (ot_[a-z_]+)\b", out))
+    missing = [n for n in _declared() if n not in exported]
+    assert not missing, missing
+    for n in _declared():
+        assert hasattr(ot.lib, n)
+
+
+def test_strerror_and_host_side_validation(ot):
+    L = ot.lib
+    assert L.ot_strerror(0) == b"success"
+    assert L.ot_strerror(-2) == b"leaves do not tile the unit cube"
+    h = ctypes.c_void_p()
+    desc = ot.TreeDesc(1, 3, 1)
+    assert L.ot_build_tree(None, None, 10, ctypes.byref(desc), None, None, ctypes.byref(h)) == -1
+    assert b"bad arguments" in L.ot_last_error()
+    # level range and capacity are checked before any device work
+    dummy = ctypes.c_void_p(0x1000)
+    bad = ot.TreeDesc(1, 22, 1)
+    assert L.ot_build_tree(dummy, dummy, 10, ctypes.byref(bad), None, None, ctypes.byref(h)) == -4
+    assert L.ot_build_tree(dummy, dummy, (1 << 26) + 1, ctypes.byref(desc), None, None, ctypes.byref(h)) == -7
+    assert L.ot_locate(None, dummy, 0, 10, dummy, None) == -1
+    assert L.ot_encode_keys(None, 0, 30, None, None) == -4
+    assert L.ot_encode_keys(None, 0, 5, None, None) == 0
+    off = (ctypes.c_int64 * 2)(0, 5)
+    ops = (ctypes.c_int32 * 1)(7)
+    assert L.ot_batch_plan_create(None, off, ops, 1, 0, 0, None, ctypes.byref(h)) == -1

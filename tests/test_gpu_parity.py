@@ -1,0 +1,356 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Host ids and sorted leaf order must match bit for bit; interpolated
+velocities, spread forces and position gradients must match within the
+stated tolerance on the magnitude-scaled metric (FP64 1e-12, FP32 1e-5),
+measured per component against sum |w| |u| (interpolate, gradient) or per leaf
+against sum |w F| (spread; FIXED mode adds its stated quantisation bound of
+2^-(s+1) per contribution).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import TOL, as_dtype, fixed_point_quantum, gpu_tree, oracle_tree, scaled_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32]
+
+
+@pytest.fixture(scope="module")
+def ot():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2605_20565_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    w = synth.workload(1)
+    return w, oracle_tree(w.tree)
+
+
+@pytest.fixture(scope="module")
+def cfg1_gpu(ot, cfg1):
+    w, _ = cfg1
+    return gpu_tree(w.tree)
+
+
+def _extra_points(rng, l_max, n=2000):
+    """Points on dyadic faces/edges/corners of the finest level, 0, 1-ulp,
+    exactly 1.0 and slightly outside the cube (wrapped when periodic)."""
+    g = rng.integers(0, 1 << l_max, (n, 3)) * math.ldexp(1.0, -l_max)
+    mix = rng.random((n, 3))
+    m = rng.random((n, 3)) < 0.5
+    mix[m] = g[m]
+    edge = np.array([[0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [np.nextafter(1.0, 0.0)] * 3, [0.5, 0.5, 0.5],
+                     [-1e-9, 0.5, 0.5], [1.0 + 1e-9, 0.25, 0.75], [-0.25, 1.5, 2.0]])
+    return np.concatenate([g, mix, edge])
+
+
+# ---------------------------------------------------------------------------
+# Tree build
+# ---------------------------------------------------------------------------
+def test_encode_keys_bitexact(ot):
+    import oracle
+    rng = np.random.default_rng(1)
+    for L in (1, 7, 10, 21):
+        a = rng.integers(0, 1 << L, (5000, 3)).astype(np.uint32)
+        got = ot.encode_keys(torch.from_numpy(a.astype(np.int32)).cuda(), L).cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, oracle.encode_keys(a, L))
+
+
+@pytest.mark.parametrize("which", ["cfg1", "rand_a", "rand_b", "deep", "lmin9"])
+def test_build_tree_order_and_perm(ot, which):
+    rng = np.random.default_rng(7)
+    if which == "cfg1":
+        spec = synth.workload(1).tree
+    elif which == "rand_a":
+        spec = synth.random_tree(1, 4, rng, 0.35)
+    elif which == "rand_b":
+        spec = synth.random_tree(0, 5, rng, 0.3, periodic=False, balance=False)
+    elif which == "deep":   # more than 3 levels below the root: several table levels
+        spec = synth.band_tree(2, 9, [synth.Sphere((0.3, 0.6, 0.5), 0.2)], seed=3)
+    else:                   # l_min above the root table level
+        spec = synth.band_tree(9, 10, [synth.Sphere((0.5, 0.5, 0.5), 0.05)], seed=4)
+    t = gpu_tree(spec)
+    o = oracle_tree(spec)
+    keys, lv = t.leaves()
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), o.keys)
+    assert np.array_equal(lv.cpu().numpy(), o.levels)
+    assert np.array_equal(t.perm.cpu().numpy().astype(np.int64), o.perm)
+    inf = t.info()
+    assert inf.n_leaves == spec.n_leaves and inf.table_levels >= 1
+
+
+def test_build_tree_rejects_bad_partitions(ot):
+    import oracle
+    spec = synth.random_tree(1, 3, np.random.default_rng(9), 0.4)
+    keys = oracle.encode_keys(spec.anchors, 3)
+    K = lambda k: torch.from_numpy(k.view(np.int64).copy()).cuda()
+    V = lambda v: torch.from_numpy(v.copy()).cuda()
+    with pytest.raises(ot.OtError) as e:
+        ot.Tree(K(keys[1:]), V(spec.levels[1:]), 1, 3)
+    assert e.value.code == -2
+    with pytest.raises(ot.OtError) as e:
+        ot.Tree(K(np.append(keys, keys[3])), V(np.append(spec.levels, spec.levels[3])), 1, 3)
+    assert e.value.code == -3
+    lv = spec.levels.copy()
+    lv[0] = 5
+    with pytest.raises(ot.OtError) as e:
+        ot.Tree(K(keys), V(lv), 1, 3)
+    assert e.value.code == -4
+    with pytest.raises(ot.OtError) as e:
+        ot.Tree(K(keys), V(spec.levels), 1, 22)
+    assert e.value.code == -4
+    # the library still works after the failures
+    t = ot.Tree(K(keys), V(spec.levels), 1, 3)
+    assert t.n_leaves == spec.n_leaves
+
+
+# ---------------------------------------------------------------------------
+# Host-cell search
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_locate_bitexact_cfg1(ot, cfg1, cfg1_gpu, dtype):
+    w, o = cfg1
+    rng = np.random.default_rng(11)
+    pts = as_dtype(np.concatenate([w.points, _extra_points(rng, 6)]), dtype)
+    ids = cfg1_gpu.locate(to_dev(pts, dtype)).cpu().numpy()
+    assert np.array_equal(ids.astype(np.int64), o.locate(pts))
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_locate_bitexact_random_trees(ot, seed, dtype):
+    rng = np.random.default_rng(200 + seed)
+    l_min = int(rng.integers(0, 3))
+    l_max = l_min + int(rng.integers(1, 5))
+    spec = synth.random_tree(l_min, l_max, rng, 0.3, periodic=bool(seed % 2), balance=seed < 2)
+    t, o = gpu_tree(spec), oracle_tree(spec)
+    pts = as_dtype(np.concatenate([rng.random((3000, 3)), _extra_points(rng, l_max)]), dtype)
+    ids = t.locate(to_dev(pts, dtype)).cpu().numpy().astype(np.int64)
+    assert np.array_equal(ids, o.locate(pts))
+    if not spec.periodic:
+        assert (ids == -1).any()
+
+
+def test_locate_nan_and_huge(ot, cfg1_gpu, cfg1):
+    _, o = cfg1
+    pts = np.array([[np.nan, 0.1, 0.1], [0.1, np.inf, 0.2], [1e300, 0.5, 0.5], [-1e300, 0.5, 0.5],
+                    [0.3, 0.3, 0.3]])
+    ids = cfg1_gpu.locate(to_dev(pts, torch.float64)).cpu().numpy()
+    assert list(ids[:4]) == [-1, -1, -1, -1]
+    assert ids[4] == o.locate(pts[4:])[0]
+
+
+# ---------------------------------------------------------------------------
+# Interpolation / spreading / fused pass
+# ---------------------------------------------------------------------------
+def _inputs(w, o, dtype, extra=True):
+    rng = np.random.default_rng(5)
+    pts = w.points if not extra else np.concatenate([w.points, _extra_points(rng, w.tree.l_max, 500)])
+    frc = np.concatenate([w.forces, rng.standard_normal((pts.shape[0] - w.forces.shape[0], 3))])
+    pts, frc = as_dtype(pts, dtype), as_dtype(frc, dtype)
+    fld = as_dtype(o.permute_rows(w.field), dtype)
+    return pts, frc, fld
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_interpolate_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
+    w, o = cfg1
+    pts, _, fld = _inputs(w, o, dtype)
+    U, S = o.interpolate(fld, pts, with_scale=True)
+    got = cfg1_gpu.interpolate(to_dev(fld, dtype), to_dev(pts, dtype)).cpu().numpy()
+    assert scaled_err(got, U, S) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_spread_atomic_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
+    w, o = cfg1
+    pts, frc, _ = _inputs(w, o, dtype)
+    f, S, cnt = o.spread(frc, pts, with_scale=True)
+    got = cfg1_gpu.spread(to_dev(frc, dtype), to_dev(pts, dtype), mode="atomic").cpu().numpy()
+    assert scaled_err(got, f, S) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_spread_fixed_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
+    w, o = cfg1
+    pts, frc, _ = _inputs(w, o, dtype)
+    f, S, cnt = o.spread(frc, pts, with_scale=True)
+    got = cfg1_gpu.spread(to_dev(frc, dtype), to_dev(pts, dtype), mode="fixed").cpu().numpy()
+    q = fixed_point_quantum(frc)
+    bound = TOL[torch.float32] * S + (cnt[:, None] * 0.5 * q) * 1.0001 + 1e-300
+    assert np.all(np.abs(got - f) <= bound)
+
+
+def test_fixed_point_is_bitwise_reproducible(ot, cfg1, cfg1_gpu):
+    w, o = cfg1
+    pts, frc, _ = _inputs(w, o, torch.float32)
+    P, F = to_dev(pts, torch.float32), to_dev(frc, torch.float32)
+    ref = cfg1_gpu.spread(F, P, mode="fixed")
+    perm = torch.randperm(P.shape[0], device=P.device)
+    for r in range(5):
+        a = cfg1_gpu.spread(F, P, mode="fixed")
+        assert torch.equal(a, ref)
+    # and independent of point order
+    b = cfg1_gpu.spread(F[perm].contiguous(), P[perm].contiguous(), mode="fixed")
+    assert torch.equal(b, ref)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_spread_accumulate_adds(ot, cfg1, cfg1_gpu, dtype):
+    w, o = cfg1
+    pts, frc, fld = _inputs(w, o, dtype)
+    P, F = to_dev(pts, dtype), to_dev(frc, dtype)
+    base = to_dev(fld, dtype)
+    for mode in ("atomic", "fixed"):
+        one = cfg1_gpu.spread(F, P, mode=mode)
+        acc = cfg1_gpu.spread(F, P, mode=mode, out=base.clone(), accumulate=True)
+        assert torch.allclose(acc, base + one, rtol=0, atol=1e-5 if dtype == torch.float32 else 1e-12)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_track_fused_matches_separate_ops(ot, cfg1, cfg1_gpu, dtype):
+    w, o = cfg1
+    pts, frc, fld = _inputs(w, o, dtype)
+    P, F, Fd = to_dev(pts, dtype), to_dev(frc, dtype), to_dev(fld, dtype)
+    ids, vel, fo = cfg1_gpu.track(P, field=Fd, force=F, mode="fixed")
+    assert torch.equal(ids, cfg1_gpu.locate(P))
+    assert torch.equal(vel, cfg1_gpu.interpolate(Fd, P))
+    assert torch.equal(fo, cfg1_gpu.spread(F, P, mode="fixed"))
+    U, S = o.interpolate(fld, pts, with_scale=True)
+    assert scaled_err(vel.cpu().numpy(), U, S) <= TOL[dtype]
+    assert np.array_equal(ids.cpu().numpy().astype(np.int64), o.locate(pts))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_nonperiodic_and_deep_tree_parity(ot, dtype):
+    """Non-periodic walls (nodes dropped) and a 7-level tree (3 table levels)."""
+    spec = synth.band_tree(2, 9, [synth.Sphere((0.3, 0.6, 0.5), 0.2), synth.Sphere((0.8, 0.2, 0.15), 0.1)],
+                           periodic=False, seed=5)
+    t, o = gpu_tree(spec), oracle_tree(spec)
+    rng = np.random.default_rng(6)
+    s = synth.Sphere((0.3, 0.6, 0.5), 0.2)
+    pts = as_dtype(np.concatenate([synth.fibonacci_sphere(s, 3000, wrap=False), rng.random((3000, 3)),
+                                   _extra_points(rng, 9, 300)]), dtype)
+    frc = as_dtype(rng.standard_normal(pts.shape), dtype)
+    fld = as_dtype(rng.standard_normal((spec.n_leaves, 3)), dtype)
+    ids, vel, fo = t.track(to_dev(pts, dtype), field=to_dev(fld, dtype), force=to_dev(frc, dtype), mode="atomic")
+    assert np.array_equal(ids.cpu().numpy().astype(np.int64), o.locate(pts))
+    U, S = o.interpolate(fld, pts, with_scale=True)
+    assert scaled_err(vel.cpu().numpy(), U, S) <= TOL[dtype]
+    f, Sf, _ = o.spread(frc, pts, with_scale=True)
+    assert scaled_err(fo.cpu().numpy(), f, Sf) <= TOL[dtype]
+
+
+def test_empty_input(ot, cfg1_gpu):
+    P = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    assert cfg1_gpu.locate(P).numel() == 0
+    fo = cfg1_gpu.spread(P, P, mode="fixed")
+    assert torch.count_nonzero(fo) == 0
+    fo = cfg1_gpu.spread(P, P, mode="atomic")
+    assert torch.count_nonzero(fo) == 0
+
+
+def test_single_leaf_tree(ot):
+    spec = synth.uniform_tree(0, seed=None)
+    t, o = gpu_tree(spec), oracle_tree(spec)
+    pts = np.random.default_rng(3).random((100, 3))
+    fld = np.array([[1.0, 2.0, 3.0]])
+    ids, vel, fo = t.track(to_dev(pts, torch.float64), field=to_dev(fld, torch.float64),
+                           force=to_dev(np.ones_like(pts), torch.float64))
+    assert (ids.cpu().numpy() == 0).all()
+    assert np.allclose(vel.cpu().numpy(), o.interpolate(fld, pts), rtol=0, atol=1e-14)
+    assert np.allclose(fo.cpu().numpy(), o.spread(np.ones_like(pts), pts), rtol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Position gradient
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_grad_pos_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
+    w, o = cfg1
+    pts, frc, fld = _inputs(w, o, dtype)
+    g, S = o.grad_pos(fld, frc, pts, with_scale=True)
+    got = cfg1_gpu.grad_pos(to_dev(fld, dtype), to_dev(frc, dtype), to_dev(pts, dtype)).cpu().numpy()
+    assert scaled_err(got, g, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
+
+
+# ---------------------------------------------------------------------------
+# Batched persistent pass
+# ---------------------------------------------------------------------------
+def _batch_case(w):
+    """Instances of the cfg1 workload (one marker set, particles split into
+    uneven groups) with mixed per-instance ops."""
+    off = [0, 1000, 1500, 1507, 4000, 11000]
+    ops = [7, 3, 1, 7, 6]
+    return off, ops
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_matches_plain_launches(ot, cfg1, cfg1_gpu, dtype):
+    w, o = cfg1
+    off, ops = _batch_case(w)
+    pts, frc, fld = _inputs(w, o, dtype, extra=False)
+    P, F, Fd = to_dev(pts, dtype), to_dev(frc, dtype), to_dev(fld, dtype)
+    n = P.shape[0]
+    for tile, block in ((256, 256), (1024, 256), (128, 64)):
+        plan = ot.BatchPlan(cfg1_gpu, off, ops, dtype=dtype, mode="fixed", block=block, tile=tile)
+        ids = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        vel = torch.full((n, 3), -7.0, dtype=dtype, device="cuda")
+        fo = torch.empty((cfg1_gpu.n_leaves, 3), dtype=dtype, device="cuda")
+        plan.run(P, field=Fd, force=F, ids=ids, vel=vel, field_out=fo)
+        torch.cuda.synchronize()
+        ref_ids = cfg1_gpu.locate(P)
+        ref_vel = cfg1_gpu.interpolate(Fd, P)
+        spread_rows = torch.zeros(n, dtype=torch.bool, device="cuda")
+        for i, op in enumerate(ops):
+            a, b = off[i], off[i + 1]
+            if op & 1:
+                assert torch.equal(ids[a:b], ref_ids[a:b])
+            else:
+                assert (ids[a:b] == -7).all()
+            if op & 2:
+                assert torch.equal(vel[a:b], ref_vel[a:b])
+            else:
+                assert (vel[a:b] == -7).all()
+            if op & 4:
+                spread_rows[a:b] = True
+        mask = spread_rows.cpu().numpy()
+        f, S, cnt = o.spread(frc[mask], pts[mask], with_scale=True)
+        q = fixed_point_quantum(frc)      # the plan's scale covers all n forces
+        bound = TOL[torch.float32] * S + cnt[:, None] * 0.5 * q * 1.0001 + 1e-300
+        assert np.all(np.abs(fo.cpu().numpy() - f) <= bound)
+        plan.close()
+
+
+def test_batch_graph_replays_are_identical(ot, cfg1, cfg1_gpu):
+    w, o = cfg1
+    pts, frc, fld = _inputs(w, o, torch.float32, extra=False)
+    P, F, Fd = to_dev(pts, torch.float32), to_dev(frc, torch.float32), to_dev(fld, torch.float32)
+    n = P.shape[0]
+    plan = ot.BatchPlan(cfg1_gpu, [0, 1000, n], [7, 7], dtype=torch.float32, mode="fixed")
+    ids = torch.empty(n, dtype=torch.int32, device="cuda")
+    vel = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    fo = torch.empty((cfg1_gpu.n_leaves, 3), dtype=torch.float32, device="cuda")
+    plan.run(P, field=Fd, force=F, ids=ids, vel=vel, field_out=fo)
+    torch.cuda.synchronize()
+    ref = (ids.clone(), vel.clone(), fo.clone())
+    eager = cfg1_gpu.spread(F, P, mode="fixed")
+    assert torch.equal(fo, eager)
+    for r in range(4):
+        ids.fill_(-1)
+        vel.zero_()
+        fo.fill_(123.0)
+        _ = cfg1_gpu.interpolate(Fd, P)          # eager work between replays
+        torch.cuda.synchronize()
+        plan.run(P, field=Fd, force=F, ids=ids, vel=vel, field_out=fo)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, ref[0]) and torch.equal(vel, ref[1]) and torch.equal(fo, ref[2])
+    plan.close()
