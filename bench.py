@@ -77,6 +77,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--no-sort", action="store_true", help="process points in input order (no in-step sort)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="points in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip side measurements")
@@ -123,7 +124,7 @@ def main():
     offsets = [int(v) for v in w.instances]
     ops = [ot.OT_OP_LOCATE | ot.OT_OP_INTERPOLATE | ot.OT_OP_SPREAD] * (len(offsets) - 1)
     plan = ot.BatchPlan(tree, offsets, ops, dtype=dt, mode=args.mode, block=args.block, tile=args.tile,
-                        grid=args.grid)
+                        grid=args.grid, sort_points=not args.no_sort)
     n_tiles, grid = plan.shape()
 
     def step():
@@ -181,7 +182,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {**workload_desc(w, args.config), "precision": args.dtype, "spread_mode": args.mode,
-                   "path": "batched persistent kernel, HIP graph", "tiles": n_tiles, "workgroups": grid},
+                   "path": "batched persistent kernel, HIP graph" + ("" if args.no_sort else
+                                                                      ", in-step sort of points by host leaf"),
+                   "tiles": n_tiles, "workgroups": grid},
         "roofline": roofline,
     }
     if not args.no_cpu:
@@ -224,7 +227,7 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
     modes = {}
     for mode in ("fixed", "atomic"):
         pl = ot.BatchPlan(tree, [int(v) for v in w.instances], [7] * (len(w.instances) - 1), dtype=dt, mode=mode,
-                          block=args.block, tile=args.tile, grid=args.grid)
+                          block=args.block, tile=args.tile, grid=args.grid, sort_points=not args.no_sort)
         ids = torch.empty(n, dtype=torch.int32, device=dev)
         vel = torch.empty((n, 3), dtype=dt, device=dev)
         fo = torch.empty((tree.n_leaves, 3), dtype=dt, device=dev)
@@ -257,7 +260,7 @@ def oracle_check(w, tree, dev, dt, torch, n_sample=20000):
     P, F, Fd = (torch.from_numpy(x).to(dev, dt) for x in (pts, frc, fld))
     ids, vel, fo = tree.track(P, field=Fd, force=F, mode="fixed")
     U, S = o.interpolate(fld, pts, with_scale=True)
-    f, Sf, _ = o.spread(frc, pts, with_scale=True)
+    f, Sf, _cnt, _A = o.spread(frc, pts, with_scale=True)
     eu = np.abs(vel.cpu().numpy() - U) / np.maximum(S, 1e-300)
     ef = np.abs(fo.cpu().numpy() - f) / np.maximum(Sf, 1e-300)
     touched = Sf > 0

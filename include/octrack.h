@@ -100,11 +100,18 @@ typedef struct {
 
 /* Tuning of the batched persistent pass. Zero fields take defaults. */
 typedef struct {
-    int32_t block;        /* threads per workgroup (multiple of 64, <= 1024)          */
+    int32_t block;        /* threads per workgroup (multiple of 64, <= 512)           */
     int32_t tile;         /* points per tile (multiple of block)                      */
     int32_t grid;         /* persistent workgroups; 0 = as many as fit on the chip    */
-    int32_t reserved;
+    int32_t flags;        /* OT_TUNE_* bits                                           */
 } ot_tuning;
+
+/* Sort the points by host leaf inside every run before the persistent pass
+ * (locate, LDS radix sort of host ids, gather of positions and forces into
+ * plan-owned buffers, pass in sorted order, scatter of velocities back).
+ * Neighbouring points then share stencil nodes in cache and in the
+ * workgroup's spreading table.  Needs the same ops for every instance. */
+#define OT_TUNE_SORT_POINTS 1
 
 /* Morton keys of leaf anchors (Sec. 3.1: leaves are ordered along the
  * Z-curve).  anchors: (n, 3) uint32, each < 2^l_max.  keys: (n,) uint64.
@@ -189,11 +196,13 @@ int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets, const int3
 int ot_batch_run(ot_batch_plan *plan, const void *field, const void *force, const void *pos,
                  int32_t *ids, void *vel, void *field_out, void *stream);
 
-/* Timing of the persistent kernel: with enable = 1 the plan records a pair
- * of HIP events just before and after its persistent kernel inside the
- * graph (on the stream the graph runs on); ot_batch_last_kernel_ms returns
- * the kernel's duration in the last completed run (OT_ERR_HIP while that run
- * is still in flight).  Changing the setting re-captures the graph. */
+/* Timing of the persistent kernel: with enable = 1, ot_batch_run enqueues
+ * the plan's sequence directly on the caller's stream (not through the
+ * graph, whose captured events cannot be timed) with a pair of HIP events
+ * recorded just before and after the persistent kernel;
+ * ot_batch_last_kernel_ms returns the kernel's duration in the last
+ * completed run (OT_ERR_HIP while it is still in flight).  enable = 0 returns
+ * to graph replays. */
 int ot_batch_plan_timing(ot_batch_plan *plan, int32_t enable);
 int ot_batch_last_kernel_ms(const ot_batch_plan *plan, float *ms);
 

@@ -62,7 +62,7 @@ def lib():
             "orc_phi": (ctypes.c_double, [ctypes.c_double]),
             "orc_dphi": (ctypes.c_double, [ctypes.c_double]),
             "orc_interpolate": (None, [TP, P, P, i64, P, P]),
-            "orc_spread": (None, [TP, P, P, i64, P, P, P]),
+            "orc_spread": (None, [TP, P, P, i64, P, P, P, P]),
             "orc_grad_pos": (None, [TP, P, P, P, i64, P, P]),
             "orc_stencil_leaves": (None, [TP, P, i64, P, P, P]),
             "orc_num_threads": (i32, []),
@@ -158,14 +158,18 @@ class Tree:
         return (U, S) if with_scale else U
 
     def spread(self, force, pos, with_scale: bool = False):
+        """f, or (f, S, count, A) with S = sum |w F|, count = contributions and
+        A = sum |F| over contributions, per leaf."""
         force = _f64(force).reshape(-1, 3)
         pos = _f64(pos).reshape(-1, 3)
         f = np.empty((self.n_leaves, 3), dtype=np.float64)
         S = np.empty_like(f) if with_scale else None
+        A = np.empty_like(f) if with_scale else None
         cnt = np.empty(self.n_leaves, dtype=np.int64) if with_scale else None
         lib().orc_spread(ctypes.byref(self._c), _p(force), _p(pos), pos.shape[0], _p(f),
-                         _p(S) if with_scale else None, _p(cnt) if with_scale else None)
-        return (f, S, cnt) if with_scale else f
+                         _p(S) if with_scale else None, _p(cnt) if with_scale else None,
+                         _p(A) if with_scale else None)
+        return (f, S, cnt, A) if with_scale else f
 
     def grad_pos(self, field, vec, pos, with_scale: bool = False):
         field = _f64(field).reshape(self.n_leaves, 3)

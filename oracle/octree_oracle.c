@@ -355,16 +355,19 @@ void orc_interpolate(const orc_tree *t, const double *field, const double *pos, 
 /* ---------------------------------------------------------------------------
  * Spreading (Sec. 2.2):  f(x_n) = sum_k F_k W(x_n - X_k) (dx)^3, the exact
  * transpose of orc_interpolate.  f, scale: (n_leaves, 3); count: contributions
- * per leaf (nullable).  f is overwritten.  Serial, points in ascending order.
+ * per leaf; fabs_sum: sum of |F_k,c| over the contributions (weight-free).
+ * The last three are nullable diagnostics.  f is overwritten.  Serial,
+ * points in ascending order.
  * ------------------------------------------------------------------------- */
 void orc_spread(const orc_tree *t, const double *F, const double *pos, int64_t n,
-                double *f, double *scale, int64_t *count)
+                double *f, double *scale, int64_t *count, double *fabs_sum)
 {
     int64_t nl = t->n_leaves;
     double *comp = (double *)calloc((size_t)(3 * nl), sizeof(double));
     memset(f, 0, sizeof(double) * 3 * (size_t)nl);
     if (scale) memset(scale, 0, sizeof(double) * 3 * (size_t)nl);
     if (count) memset(count, 0, sizeof(int64_t) * (size_t)nl);
+    if (fabs_sum) memset(fabs_sum, 0, sizeof(double) * 3 * (size_t)nl);
     for (int64_t k = 0; k < n; ++k) {
         stencil st;
         if (!build_stencil(t, pos + 3 * k, &st)) continue;
@@ -378,6 +381,7 @@ void orc_spread(const orc_tree *t, const double *F, const double *pos, int64_t n
                     for (int e = 0; e < 3; ++e) {
                         nsum(&f[3 * j + e], &comp[3 * j + e], w * F[3 * k + e]);
                         if (scale) scale[3 * j + e] += fabs(w * F[3 * k + e]);
+                        if (fabs_sum) fabs_sum[3 * j + e] += fabs(F[3 * k + e]);
                     }
                     if (count) count[j] += 1;
                 }

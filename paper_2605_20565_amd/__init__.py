@@ -46,7 +46,10 @@ class TreeInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
+
+
+OT_TUNE_SORT_POINTS = 1
 
 
 EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_get", "ot_tree_leaves",
@@ -287,10 +290,10 @@ class BatchPlan:
     """Many point sets in one persistent, graph-replayed pass (``ot_batch_*``)."""
 
     def __init__(self, tree: Tree, offsets: Sequence[int], ops: Sequence[int], dtype=torch.float32,
-                 mode="atomic", block: int = 0, tile: int = 0, grid: int = 0):
+                 mode="atomic", block: int = 0, tile: int = 0, grid: int = 0, sort_points: bool = False):
         off = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
         opa = (ctypes.c_int32 * len(ops))(*[int(v) for v in ops])
-        tun = Tuning(block, tile, grid, 0)
+        tun = Tuning(block, tile, grid, OT_TUNE_SORT_POINTS if sort_points else 0)
         h = ctypes.c_void_p()
         code = OT_F32 if dtype == torch.float32 else OT_F64
         _check(lib.ot_batch_plan_create(tree.handle, off, opa, len(ops), code, _mode_code(mode), ctypes.byref(tun),

@@ -37,6 +37,14 @@ struct ot_batch_plan {
     const void *key[6];
     bool timing;              // record ev[0]/ev[1] around the persistent kernel
     hipEvent_t ev[2];
+    // point sorting (OT_TUNE_SORT_POINTS)
+    bool sort_points;
+    int sort_bits;
+    int ops_all;              // the common ops of every instance
+    uint64_t *skey[2];
+    int32_t *sval[2];
+    void *sws;                // radix sort workspace
+    void *spos, *sforce, *svel;
 };
 
 namespace ot {
@@ -45,14 +53,22 @@ namespace {
 constexpr uint32_t kCountMask = 0x00FFFFFFu;
 
 template <typename T, int MODE>
-__global__ void k_batch(TreeView tv, const int64_t *__restrict__ tile_start, const uint32_t *__restrict__ tile_info,
-                        int64_t n_tiles, unsigned *__restrict__ counter, const T *__restrict__ pos,
-                        const T *__restrict__ field, const T *__restrict__ force, int32_t *__restrict__ ids,
-                        T *__restrict__ vel, T *__restrict__ fout, unsigned long long *__restrict__ facc,
-                        const FxState *__restrict__ fx)
+__global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__restrict__ tile_start,
+                                               const uint32_t *__restrict__ tile_info, int64_t n_tiles,
+                                               unsigned *__restrict__ counter, const T *__restrict__ pos,
+                                               const T *__restrict__ field, const T *__restrict__ force,
+                                               int32_t *__restrict__ ids, T *__restrict__ vel, T *__restrict__ fout,
+                                               unsigned long long *__restrict__ facc, const FxState *__restrict__ fx)
 {
+    constexpr int S = SinkSlots<T, MODE>::value;
+    using Acc = typename AccType<T, MODE>::type;
+    __shared__ uint32_t keys[S];
+    __shared__ Acc vals[3 * S];
+    __shared__ uint32_t used;
     __shared__ unsigned s_tile;
     const double scale = MODE == kModeFixed ? fx->scale : 0.0;
+    LdsSink<T, MODE, S> sink{keys, vals, &used, fout, facc, scale};
+    sink.clear();
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
         __syncthreads();
@@ -61,19 +77,57 @@ __global__ void k_batch(TreeView tv, const int64_t *__restrict__ tile_start, con
         if (tile >= n_tiles) break;   // same value in every thread of the workgroup
         const int64_t start = tile_start[tile];
         const uint32_t info = tile_info[tile];
-        const int cnt = (int)(info & kCountMask);
-        const int ops = (int)(info >> 24);
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-            const int64_t k = start + i;
-            switch (ops) {
+        const int64_t end = start + (int64_t)(info & kCountMask);
+        switch (info >> 24) {
 #define OT_CASE(OPSV) \
-    case OPSV: track_point<T, OPSV, MODE>(tv, k, pos, field, force, ids, vel, fout, facc, scale); break;
-                OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
+    case OPSV: track_range<T, OPSV>(tv, start, end, pos, field, force, ids, vel, sink); break;
+            OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
 #undef OT_CASE
-            default: break;
-            }
+        default: break;
         }
+        sink.maybe_flush();
     }
+    sink.flush();
+}
+
+// Sort keys: host leaf id (n_leaves for points without a host, so they
+// sort last); values: the point's index.  Writes ids when asked.
+template <typename T>
+__global__ void k_sort_keys(TreeView tv, int64_t n, const T *__restrict__ pos, int32_t *__restrict__ ids,
+                            uint64_t *__restrict__ keys, int32_t *__restrict__ vals, uint32_t none)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t I[3];
+    const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
+    const uint32_t host = ok ? (descend(tv, I[0], I[1], I[2]) & kIdMask) : none;
+    if (ids) ids[k] = ok ? (int32_t)host : -1;
+    keys[k] = host;
+    vals[k] = (int32_t)k;
+}
+
+template <typename T>
+__global__ void k_gather_rows(const int32_t *__restrict__ perm, const T *__restrict__ src, T *__restrict__ dst,
+                              int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = 3 * (int64_t)perm[i];
+    dst[3 * i] = src[j];
+    dst[3 * i + 1] = src[j + 1];
+    dst[3 * i + 2] = src[j + 2];
+}
+
+template <typename T>
+__global__ void k_scatter_rows(const int32_t *__restrict__ perm, const T *__restrict__ src, T *__restrict__ dst,
+                               int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = 3 * (int64_t)perm[i];
+    dst[j] = src[3 * i];
+    dst[j + 1] = src[3 * i + 1];
+    dst[j + 2] = src[3 * i + 2];
 }
 
 template <typename T, int MODE>
@@ -81,18 +135,44 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
             void *fout, hipStream_t s)
 {
     const ot_tree *t = p->tree;
+    const int64_t n = p->n_points;
     hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, p->counter, (int64_t)1, 0u);
     int rc;
     if (p->ops_union & kOpSpread)
-        if ((rc = spread_prologue(t, p->dtype, p->mode, 0, force, p->n_points, fout, s))) return rc;
+        if ((rc = spread_prologue(t, p->dtype, p->mode, 0, force, n, fout, s))) return rc;
+    const T *kpos = (const T *)pos, *kforce = (const T *)force;
+    T *kvel = (T *)vel;
+    int32_t *kids = ids;
+    const int32_t *perm = nullptr;
+    if (p->sort_points && n > 0) {
+        const unsigned gb = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(k_sort_keys<T>, dim3(gb), dim3(256), 0, s, t->view, n, (const T *)pos,
+                           (p->ops_all & kOpLocate) ? ids : (int32_t *)nullptr, p->skey[0], p->sval[0],
+                           (uint32_t)t->n_leaves);
+        uint64_t *kr;
+        int32_t *vr;
+        radix_sort_pairs(p->skey[0], p->sval[0], p->skey[1], p->sval[1], n, p->sort_bits, p->sws, &kr, &vr, s);
+        perm = vr;
+        hipLaunchKernelGGL(k_gather_rows<T>, dim3(gb), dim3(256), 0, s, perm, (const T *)pos, (T *)p->spos, n);
+        if (p->ops_all & kOpSpread)
+            hipLaunchKernelGGL(k_gather_rows<T>, dim3(gb), dim3(256), 0, s, perm, (const T *)force, (T *)p->sforce, n);
+        kpos = (const T *)p->spos;
+        kforce = (const T *)p->sforce;
+        kvel = (T *)p->svel;
+        kids = nullptr;
+    }
     if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
     hipLaunchKernelGGL((k_batch<T, MODE>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start, p->tile_info,
-                       p->n_tiles, p->counter, (const T *)pos, (const T *)field, (const T *)force, ids, (T *)vel,
-                       (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+                       p->n_tiles, p->counter, kpos, (const T *)field, kforce, kids, kvel, (T *)fout, t->fx_acc,
+                       (const FxState *)t->scratch);
     OT_HIP(hipGetLastError());
     if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
+    if (perm && (p->ops_all & kOpInterp))
+        hipLaunchKernelGGL(k_scatter_rows<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, perm,
+                           (const T *)p->svel, (T *)vel, n);
     if (p->ops_union & kOpSpread)
         if ((rc = spread_epilogue(t, p->dtype, p->mode, 0, fout, s))) return rc;
+    OT_HIP(hipGetLastError());
     return OT_OK;
 }
 
@@ -128,24 +208,40 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     if (!tree || !offsets || !ops || n_inst <= 0) return fail(OT_ERR_INVALID, "ot_batch_plan_create: bad arguments");
     if (dtype != OT_F32 && dtype != OT_F64) return fail(OT_ERR_INVALID, "dtype must be OT_F32 or OT_F64");
     if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
-    int block = tuning && tuning->block ? tuning->block : 256;
+    int block = tuning && tuning->block ? tuning->block : 512;
     int tile = tuning && tuning->tile ? tuning->tile : 4 * block;
-    if (block < 64 || block > 1024 || block % 64) return fail(OT_ERR_INVALID, "block must be a multiple of 64 in [64, 1024]");
+    if (block < 64 || block > 512 || block % 64) return fail(OT_ERR_INVALID, "block must be a multiple of 64 in [64, 512]");
     if (tile < block || tile % block || tile > (int)kCountMask) return fail(OT_ERR_INVALID, "tile must be a multiple of block");
     if (offsets[0] != 0) return fail(OT_ERR_INVALID, "offsets[0] must be 0");
+    const bool sort_points = tuning && (tuning->flags & OT_TUNE_SORT_POINTS);
     std::vector<int64_t> starts;
     std::vector<uint32_t> infos;
-    int ops_union = 0;
+    int ops_union = 0, ops_all = -1;
     for (int i = 0; i < n_inst; ++i) {
         if (offsets[i + 1] < offsets[i]) return fail(OT_ERR_INVALID, "offsets must be ascending");
         if (ops[i] < 0 || ops[i] > 7) return fail(OT_ERR_INVALID, "bad per-instance ops");
-        if (ops[i] == 0) continue;
+        if (ops[i] == 0 || offsets[i + 1] == offsets[i]) continue;
         ops_union |= ops[i];
+        if (ops_all >= 0 && ops_all != ops[i] && sort_points)
+            return fail(OT_ERR_INVALID, "point sorting needs the same ops for every instance");
+        ops_all = ops[i];
+        if (sort_points) continue;
         for (int64_t a = offsets[i]; a < offsets[i + 1]; a += tile) {
             const int64_t c = std::min<int64_t>(tile, offsets[i + 1] - a);
             starts.push_back(a);
             infos.push_back((uint32_t)c | ((uint32_t)ops[i] << 24));
         }
+    }
+    if (ops_all < 0) ops_all = 0;
+    if (sort_points) {
+        // one run of tiles over the sorted points; ids were written by the sort-key pass
+        const int sops = ops_all & ~kOpLocate;
+        const int64_t n = offsets[n_inst];
+        if (sops)
+            for (int64_t a = 0; a < n; a += tile) {
+                starts.push_back(a);
+                infos.push_back((uint32_t)std::min<int64_t>(tile, n - a) | ((uint32_t)sops << 24));
+            }
     }
     ot_batch_plan *p = new ot_batch_plan();
     p->tree = tree;
@@ -157,11 +253,38 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     p->n_points = offsets[n_inst];
     p->n_tiles = (int64_t)starts.size();
     p->have_graph = false;
+    p->sort_points = sort_points;
+    p->ops_all = ops_all;
+    if (sort_points && p->n_points > 0) {
+        const int64_t n = p->n_points;
+        int bits = 1;
+        while ((int64_t(1) << bits) <= tree->n_leaves) ++bits;   // keys go up to n_leaves
+        p->sort_bits = bits;
+        const size_t row = (dtype == OT_F32 ? 4 : 8) * 3 * (size_t)n;
+        hipError_t e = hipSuccess;
+        if (e == hipSuccess) e = hipMalloc((void **)&p->skey[0], 8 * (size_t)n);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->skey[1], 8 * (size_t)n);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->sval[0], 4 * (size_t)n);
+        if (e == hipSuccess) e = hipMalloc((void **)&p->sval[1], 4 * (size_t)n);
+        if (e == hipSuccess) e = hipMalloc(&p->sws, (size_t)radix_ws_bytes(n));
+        if (e == hipSuccess) e = hipMalloc(&p->spos, row);
+        if (e == hipSuccess && (ops_all & kOpSpread)) e = hipMalloc(&p->sforce, row);
+        if (e == hipSuccess && (ops_all & kOpInterp)) e = hipMalloc(&p->svel, row);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ot_batch_plan_destroy(p);
+            return fail(OT_ERR_OOM, "ot_batch_plan_create: sort buffers");
+        }
+    }
     int cus = 0, dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per_cu = 0;
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_batch<float, kModeAtomic>, block, 0);
+    const void *kfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? (const void *)k_batch<float, kModeFixed>
+                                                                 : (const void *)k_batch<float, kModeAtomic>)
+                                      : (mode == OT_SPREAD_FIXED ? (const void *)k_batch<double, kModeFixed>
+                                                                 : (const void *)k_batch<double, kModeAtomic>);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, block, 0);
     if (per_cu <= 0) per_cu = 1;
     int grid = tuning && tuning->grid ? tuning->grid : std::max(1, cus) * per_cu;
     if (p->n_tiles > 0 && grid > p->n_tiles) grid = (int)p->n_tiles;
@@ -202,6 +325,11 @@ extern "C" int ot_batch_run(ot_batch_plan *p, const void *field, const void *for
     if ((u & kOpInterp) && (!field || !vel)) return fail(OT_ERR_INVALID, "field or vel is NULL");
     if ((u & kOpSpread) && (!force || !field_out)) return fail(OT_ERR_INVALID, "force or field_out is NULL");
     hipStream_t s = (hipStream_t)stream;
+    if (p->timing) {
+        // Events recorded inside a captured graph cannot be timed, so a timed
+        // run enqueues the same sequence directly on the caller's stream.
+        return enqueue_any(p, field, force, pos, ids, vel, field_out, s);
+    }
     const void *key[6] = {field, force, pos, ids, vel, field_out};
     if (!p->have_graph || std::memcmp(key, p->key, sizeof(key)) != 0) {
         drop_graph(p);
@@ -242,7 +370,6 @@ extern "C" int ot_batch_plan_timing(ot_batch_plan *p, int32_t enable)
     if (!p) return fail(OT_ERR_INVALID, "plan is NULL");
     const bool on = enable != 0;
     if (on == p->timing) return OT_OK;
-    drop_graph(p);
     if (on && !p->ev[0]) {
         OT_HIP(hipEventCreate(&p->ev[0]));
         OT_HIP(hipEventCreate(&p->ev[1]));
@@ -266,6 +393,9 @@ extern "C" int ot_batch_plan_destroy(ot_batch_plan *p)
     drop_graph(p);
     if (p->ev[0]) (void)hipEventDestroy(p->ev[0]);
     if (p->ev[1]) (void)hipEventDestroy(p->ev[1]);
+    for (void *q : {(void *)p->skey[0], (void *)p->skey[1], (void *)p->sval[0], (void *)p->sval[1], p->sws, p->spos,
+                    p->sforce, p->svel})
+        if (q) (void)hipFree(q);
     if (p->tile_start) (void)hipFree(p->tile_start);
     if (p->tile_info) (void)hipFree(p->tile_info);
     if (p->counter) (void)hipFree(p->counter);

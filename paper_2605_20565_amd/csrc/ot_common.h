@@ -99,20 +99,26 @@ __device__ __forceinline__ bool point_cell(const TreeView &tv, T x, T y, T z, ui
 
 // 1-D weights of the three stencil nodes i0-1, i0, i0+1 for a point at
 // fractional offset t in [0,1) inside its level-l cell.  With u = t - 1/2
-// the node distances are u+1, u, u-1 and all three branches of phi share
-// q = sqrt(1 - 3u^2):
-//   phi(u+1) = (2 - 3u - q)/6,  phi(u) = (1 + q)/3,  phi(u-1) = (2 + 3u - q)/6
-// (substituting |r| = 1+u, |u|, 1-u into the phi equation of Sec. 2.2;
-// -2 + 6|r| - 3r^2 = 1 - 3u^2 for |r| = 1 +- u).  Derivatives d/du:
-//   (-1 + u/q)/2,  -u/q,  (1 + u/q)/2.
+// the node distances are u+1, u, u-1, and all three branches of phi share
+// q = sqrt(1 - 3u^2) (substitute |r| = 1+u, |u|, 1-u into the phi equation of
+// Sec. 2.2; -2 + 6|r| - 3r^2 = 1 - 3u^2 for |r| = 1 -+ u):
+//   phi(u+1) = (2 - 3u - q)/6,  phi(u) = (1 + q)/3,  phi(u-1) = (2 + 3u - q)/6.
+// The outer two lose all their digits to cancellation near the edge of the
+// support; multiplying by the conjugate gives forms without cancellation,
+//   (2 -+ 3u - q)/6 = (1 -+ 2u)^2 / (2 (2 -+ 3u + q)),  1 + 2u = 2t, 1 - 2u = 2(1-t),
+// so every weight is accurate to a few ulp relative.  Derivatives d/du:
+//   (u - q)/(2q),  -u/q,  (u + q)/(2q),
+// with u -+ q rewritten the same way where it cancels
+// (u - q = -4t(1-t)/(u+q) for u >= 0, u + q = 4t(1-t)/(q-u) for u < 0).
 template <typename T>
 __device__ __forceinline__ void delta3(T t, T w[3])
 {
     const T u = t - T(0.5);
     const T q = sqrt(T(1) - T(3) * u * u);
-    w[0] = (T(2) - T(3) * u - q) * T(1.0 / 6.0);
+    const T s = T(1) - t;
+    w[0] = T(2) * s * s / (T(2) - T(3) * u + q);
     w[1] = (T(1) + q) * T(1.0 / 3.0);
-    w[2] = (T(2) + T(3) * u - q) * T(1.0 / 6.0);
+    w[2] = T(2) * t * t / (T(2) + T(3) * u + q);
 }
 
 template <typename T>
@@ -120,19 +126,28 @@ __device__ __forceinline__ void delta3_grad(T t, T w[3], T dw[3])
 {
     const T u = t - T(0.5);
     const T q = sqrt(T(1) - T(3) * u * u);
-    const T uq = u / q;
-    w[0] = (T(2) - T(3) * u - q) * T(1.0 / 6.0);
+    const T s = T(1) - t;
+    w[0] = T(2) * s * s / (T(2) - T(3) * u + q);
     w[1] = (T(1) + q) * T(1.0 / 3.0);
-    w[2] = (T(2) + T(3) * u - q) * T(1.0 / 6.0);
-    dw[0] = (uq - T(1)) * T(0.5);
-    dw[1] = -uq;
-    dw[2] = (uq + T(1)) * T(0.5);
+    w[2] = T(2) * t * t / (T(2) + T(3) * u + q);
+    const T ts = t * s;
+    dw[0] = u < T(0) ? (u - q) / (T(2) * q) : T(-2) * ts / (q * (u + q));
+    dw[1] = -u / q;
+    dw[2] = u < T(0) ? T(2) * ts / (q * (q - u)) : (u + q) / (T(2) * q);
 }
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 void set_error(const std::string &msg);
+
+// Device-wide helpers (tree_build.hip): exclusive scan of uint32 and the
+// LDS-staged LSD radix sort of (uint64 key, int32 value) pairs.
+int64_t scan_tmp_words(int64_t n);
+void exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+int64_t radix_ws_bytes(int64_t n);
+void radix_sort_pairs(uint64_t *k0, int32_t *v0, uint64_t *k1, int32_t *v1, int64_t n, int bits, void *ws,
+                      uint64_t **k_res, int32_t **v_res, hipStream_t s);
 int fail(int code, const std::string &msg);
 int hip_fail(hipError_t e, const char *what);
 

@@ -16,17 +16,33 @@ namespace ot {
 
 namespace {
 
+// One workgroup per tile of `tile` consecutive points.  Spreading goes
+// through the workgroup's LDS aggregation table, flushed once at the end.
 template <typename T, int OPS, int MODE>
-__global__ __launch_bounds__(256) void k_track(TreeView tv, int64_t n, const T *__restrict__ pos,
+__global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t tile, const T *__restrict__ pos,
                                                const T *__restrict__ field, const T *__restrict__ force,
                                                int32_t *__restrict__ ids, T *__restrict__ vel,
                                                T *__restrict__ fout, unsigned long long *__restrict__ facc,
                                                const FxState *__restrict__ fx)
 {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const double scale = (OPS & kOpSpread) && MODE == kModeFixed ? fx->scale : 0.0;
-    track_point<T, OPS, MODE>(tv, k, pos, field, force, ids, vel, fout, facc, scale);
+    const int64_t start = (int64_t)blockIdx.x * tile;
+    const int64_t end = start + tile < n ? start + tile : n;
+    if constexpr ((OPS & kOpSpread) != 0) {
+        constexpr int S = SinkSlots<T, MODE>::value;
+        using Acc = typename AccType<T, MODE>::type;
+        __shared__ uint32_t keys[S];
+        __shared__ Acc vals[3 * S];
+        __shared__ uint32_t used;
+        const double scale = MODE == kModeFixed ? fx->scale : 0.0;
+        LdsSink<T, MODE, S> sink{keys, vals, &used, fout, facc, scale};
+        sink.clear();
+        __syncthreads();
+        track_range<T, OPS>(tv, start, end, pos, field, force, ids, vel, sink);
+        sink.flush();
+    } else {
+        DirectSink<T, MODE> sink{fout, facc, 0.0};
+        track_range<T, OPS>(tv, start, end, pos, field, force, ids, vel, sink);
+    }
 }
 
 template <typename T>
@@ -39,6 +55,8 @@ __global__ __launch_bounds__(256) void k_grad(TreeView tv, int64_t n, const T *_
     grad_point<T>(tv, k, pos, field, vec, grad);
 }
 
+constexpr int kPointsPerThread = 4;
+
 template <typename T, int MODE>
 int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, hipStream_t s, int64_t n, const void *pos,
                  const void *field, const void *force, int32_t *ids, void *vel, void *fout)
@@ -46,8 +64,10 @@ int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, hipStream_t s, int64
     const T *P = (const T *)pos, *Fd = (const T *)field, *Fo = (const T *)force;
     T *V = (T *)vel, *O = (T *)fout;
     const FxState *fx = (const FxState *)t->scratch;
-#define OT_LAUNCH(OPSV)                                                                                  \
-    hipLaunchKernelGGL((k_track<T, OPSV, MODE>), g, b, 0, s, t->view, n, P, Fd, Fo, ids, V, O, t->fx_acc, fx); \
+    const int64_t tile = (int64_t)b.x * kPointsPerThread;
+#define OT_LAUNCH(OPSV)                                                                                        \
+    hipLaunchKernelGGL((k_track<T, OPSV, MODE>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O, t->fx_acc, \
+                       fx);                                                                                    \
     break;
     switch (ops) {
     case 1: OT_LAUNCH(1)
@@ -133,7 +153,9 @@ int track(const ot_tree *t, int ops, const void *field, const void *force, const
         if ((rc = spread_prologue(t, dtype, mode, accumulate, force, n, fout, s))) return rc;
     }
     if (n > 0) {
-        dim3 b(256), g((unsigned)((n + 255) / 256));
+        const int threads = (ops & kOpSpread) ? 512 : 256;
+        const int64_t tile = (int64_t)threads * kPointsPerThread;
+        dim3 b(threads), g((unsigned)((n + tile - 1) / tile));
         if (dtype == OT_F32)
             rc = mode == OT_SPREAD_FIXED ? dispatch_ops<float, kModeFixed>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout)
                                          : dispatch_ops<float, kModeAtomic>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout);

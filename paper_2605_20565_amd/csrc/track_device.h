@@ -24,12 +24,29 @@ struct FxState {
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-// Stencil of one point: host entry, 1-D weights and the node-centre integer
-// coordinates (finest level) of the three node cells per axis.
+// Table entry below a SPLIT root entry: continue the descent at level 1.
+__device__ __forceinline__ uint32_t descend_below_root(const TreeView &tv, uint32_t e, uint32_t ix, uint32_t iy,
+                                                       uint32_t iz)
+{
+    for (int t = 1; t < tv.nlev && (e & kSplit); ++t) {
+        const int d = tv.lev[t] - tv.lev[t - 1];
+        const int s = tv.L - tv.lev[t];
+        const uint32_t m = (1u << d) - 1u;
+        const uint32_t sub = interleave3((ix >> s) & m, (iy >> s) & m, (iz >> s) & m);
+        e = __ldg(tv.table + tv.off[t] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
+    }
+    return e;
+}
+
+// Stencil of one point: host entry, 1-D weights, and per axis the three node
+// cells' centre coordinates at the finest level (N) and their root-table
+// digits already spread for Morton interleaving (R), so that the root index
+// of node (ox, oy, oz) is R[0][ox] | R[1][oy] << 1 | R[2][oz] << 2.
 template <typename T>
 struct Stencil {
     T w[3][3];
     uint32_t N[3][3];
+    uint32_t R[3][3];
     uint32_t valid;      // bit (d*3 + o) set when node o of axis d exists
     int level;
     uint32_t host;
@@ -41,6 +58,7 @@ __device__ __forceinline__ void make_stencil(const TreeView &tv, const T X[3], c
 {
     const int l = (int)((e >> kLevelShift) & 31u);
     const int sh = tv.L - l;
+    const int rs = tv.L - tv.lev[0];
     const int32_t Ml = 1 << l;
     const uint32_t half = sh > 0 ? (1u << (sh - 1)) : 0u;
     const T sc = (T)Ml;   // 2^l, exact
@@ -58,17 +76,154 @@ __device__ __forceinline__ void make_stencil(const TreeView &tv, const T X[3], c
             bool ok = true;
             if (tv.periodic) nn &= (Ml - 1);
             else ok = (nn >= 0) && (nn < Ml);
-            st.N[d][o] = ((uint32_t)nn << sh) | half;
+            const uint32_t Nc = ((uint32_t)nn << sh) | half;
+            st.N[d][o] = Nc;
+            st.R[d][o] = part1by2(Nc >> rs);
             st.valid |= (ok ? 1u : 0u) << (d * 3 + o);
         }
     }
 }
 
-template <typename T, int OPS, int MODE>
+template <typename T>
+__device__ __forceinline__ uint32_t node_leaf(const TreeView &tv, const Stencil<T> &st, int ox, int oy, int oz)
+{
+    uint32_t e = __ldg(tv.table + (st.R[0][ox] | (st.R[1][oy] << 1) | (st.R[2][oz] << 2)));
+    if (e & kSplit) e = descend_below_root(tv, e, st.N[0][ox], st.N[1][oy], st.N[2][oz]);
+    return e & kIdMask;
+}
+
+// ---------------------------------------------------------------------------
+// Spreading sinks: where the contributions w F of one point go.
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+struct AccType { using type = T; };
+template <typename T>
+struct AccType<T, kModeFixed> { using type = unsigned long long; };
+
+template <typename T, int MODE>
+__device__ __forceinline__ typename AccType<T, MODE>::type to_acc(T v, double scale)
+{
+    if constexpr (MODE == kModeFixed) return (unsigned long long)__double2ll_rn((double)v * scale);
+    else return v;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void global_add(T *fout, unsigned long long *facc, int64_t j,
+                                           typename AccType<T, MODE>::type v)
+{
+    if constexpr (MODE == kModeFixed) atomicAdd(facc + j, v);
+    else atomic_add(fout + j, v);
+}
+
+// Straight to device memory with one atomic per component.
+template <typename T, int MODE>
+struct DirectSink {
+    T *fout;
+    unsigned long long *facc;
+    double scale;
+    __device__ __forceinline__ void add(uint32_t leaf, T w, const T F[3])
+    {
+        const int64_t j = 3 * (int64_t)leaf;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) global_add<T, MODE>(fout, facc, j + c, to_acc<T, MODE>(w * F[c], scale));
+    }
+};
+
+// Workgroup-local aggregation: an open-addressing table in LDS keyed by leaf
+// id (slot = id mod S, linear probing) accumulates the contributions of all
+// points the workgroup handles; flush() adds each occupied slot to device
+// memory once.  Slots follow the ids, so the flush's atomics come in runs of
+// neighbouring addresses.  A contribution that finds no slot within kProbe
+// steps goes straight to device memory.  In FIXED mode every value is the
+// same rounded integer either way, so the result does not depend on the path.
+template <typename T, int MODE, int S>
+struct LdsSink {
+    using Acc = typename AccType<T, MODE>::type;
+    static constexpr int kProbe = 8;
+    uint32_t *keys;     // S, 0 = empty, else leaf + 1
+    Acc *vals;          // 3 S
+    uint32_t *used;     // occupied slots
+    T *fout;
+    unsigned long long *facc;
+    double scale;
+
+    __device__ __forceinline__ void clear()
+    {
+        for (int i = threadIdx.x; i < S; i += blockDim.x) {
+            keys[i] = 0u;
+            vals[3 * i] = Acc(0);
+            vals[3 * i + 1] = Acc(0);
+            vals[3 * i + 2] = Acc(0);
+        }
+        if (threadIdx.x == 0) *used = 0u;
+    }
+
+    __device__ __forceinline__ void add(uint32_t leaf, T w, const T F[3])
+    {
+        const uint32_t key = leaf + 1u;
+        uint32_t slot = leaf & (S - 1);
+        const Acc a0 = to_acc<T, MODE>(w * F[0], scale);
+        const Acc a1 = to_acc<T, MODE>(w * F[1], scale);
+        const Acc a2 = to_acc<T, MODE>(w * F[2], scale);
+#pragma unroll 1
+        for (int p = 0; p < kProbe; ++p) {
+            uint32_t cur = keys[slot];
+            if (cur == 0u) {
+                cur = atomicCAS(&keys[slot], 0u, key);
+                if (cur == 0u) {
+                    cur = key;
+                    atomicAdd(used, 1u);
+                }
+            }
+            if (cur == key) {
+                atomicAdd(&vals[3 * slot], a0);
+                atomicAdd(&vals[3 * slot + 1], a1);
+                atomicAdd(&vals[3 * slot + 2], a2);
+                return;
+            }
+            slot = (slot + 1u) & (S - 1);
+        }
+        const int64_t j = 3 * (int64_t)leaf;
+        global_add<T, MODE>(fout, facc, j, a0);
+        global_add<T, MODE>(fout, facc, j + 1, a1);
+        global_add<T, MODE>(fout, facc, j + 2, a2);
+    }
+
+    // All threads of the workgroup; leaves the table empty.
+    __device__ __forceinline__ void flush()
+    {
+        __syncthreads();
+        for (int i = threadIdx.x; i < S; i += blockDim.x) {
+            const uint32_t key = keys[i];
+            if (key) {
+                const int64_t j = 3 * (int64_t)(key - 1u);
+                global_add<T, MODE>(fout, facc, j, vals[3 * i]);
+                global_add<T, MODE>(fout, facc, j + 1, vals[3 * i + 1]);
+                global_add<T, MODE>(fout, facc, j + 2, vals[3 * i + 2]);
+                keys[i] = 0u;
+                vals[3 * i] = Acc(0);
+                vals[3 * i + 1] = Acc(0);
+                vals[3 * i + 2] = Acc(0);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) *used = 0u;
+        __syncthreads();
+    }
+
+    // Flush when the table is getting full (all threads of the workgroup).
+    __device__ __forceinline__ void maybe_flush()
+    {
+        __syncthreads();
+        const uint32_t u = *used;
+        if (u > (uint32_t)(S * 3 / 8)) flush();
+    }
+};
+
+template <typename T, int OPS, typename Sink>
 __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const T *__restrict__ pos,
                                             const T *__restrict__ field, const T *__restrict__ force,
-                                            int32_t *__restrict__ ids, T *__restrict__ vel, T *__restrict__ fout,
-                                            unsigned long long *__restrict__ facc, double fx_scale)
+                                            int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink)
 {
     const T X[3] = {pos[3 * k], pos[3 * k + 1], pos[3 * k + 2]};
     uint32_t I[3];
@@ -96,30 +251,16 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
                 for (int ox = 0; ox < 3; ++ox) {
                     const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
                     if ((st.valid & need) != need) continue;
-                    uint32_t leaf;
-                    if (ox == 1 && oy == 1 && oz == 1) leaf = st.host;   // the centre node lies in the host
-                    else leaf = descend(tv, st.N[0][ox], st.N[1][oy], st.N[2][oz]) & kIdMask;
+                    // the centre node lies in the host leaf
+                    const uint32_t leaf = (ox == 1 && oy == 1 && oz == 1) ? st.host : node_leaf<T>(tv, st, ox, oy, oz);
                     const T w = st.w[0][ox] * wyz;
-                    const int64_t j = 3 * (int64_t)leaf;
                     if (OPS & kOpInterp) {
+                        const int64_t j = 3 * (int64_t)leaf;
                         U[0] += w * field[j];
                         U[1] += w * field[j + 1];
                         U[2] += w * field[j + 2];
                     }
-                    if (OPS & kOpSpread) {
-                        if (MODE == kModeFixed) {
-#pragma unroll
-                            for (int c = 0; c < 3; ++c) {
-                                const T v = w * F[c];
-                                const long long q = __double2ll_rn((double)v * fx_scale);
-                                atomicAdd(facc + j + c, (unsigned long long)q);
-                            }
-                        } else {
-                            atomic_add(fout + j, w * F[0]);
-                            atomic_add(fout + j + 1, w * F[1]);
-                            atomic_add(fout + j + 2, w * F[2]);
-                        }
-                    }
+                    if (OPS & kOpSpread) sink.add(leaf, w, F);
                 }
             }
         }
@@ -164,9 +305,7 @@ __device__ __forceinline__ void grad_point(const TreeView &tv, int64_t k, const 
                 for (int ox = 0; ox < 3; ++ox) {
                     const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
                     if ((st.valid & need) != need) continue;
-                    uint32_t leaf;
-                    if (ox == 1 && oy == 1 && oz == 1) leaf = st.host;
-                    else leaf = descend(tv, st.N[0][ox], st.N[1][oy], st.N[2][oz]) & kIdMask;
+                    const uint32_t leaf = (ox == 1 && oy == 1 && oz == 1) ? st.host : node_leaf<T>(tv, st, ox, oy, oz);
                     const int64_t j = 3 * (int64_t)leaf;
                     const T dot = v0 * field[j] + v1 * field[j + 1] + v2 * field[j + 2];
                     G[0] += dot * dw[0][ox] * st.w[1][oy] * st.w[2][oz];
@@ -246,5 +385,20 @@ __global__ void k_fx_finalize(const unsigned long long *__restrict__ acc, T *__r
         out[i] = accumulate ? out[i] + v : v;
     }
 }
+
+// Process points [start, end) of one tile with all threads of the workgroup.
+template <typename T, int OPS, typename Sink>
+__device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, int64_t end, const T *__restrict__ pos,
+                                            const T *__restrict__ field, const T *__restrict__ force,
+                                            int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink)
+{
+    for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x)
+        track_point<T, OPS, Sink>(tv, k, pos, field, force, ids, vel, sink);
+}
+
+// LDS table size of the aggregating sink, per precision and mode
+// (FIXED and FP64 slots hold 3 x 8 bytes, FP32 atomic slots 3 x 4 bytes).
+template <typename T, int MODE>
+struct SinkSlots { static constexpr int value = (MODE == kModeFixed || sizeof(T) == 8) ? 2048 : 4096; };
 
 }  // namespace ot

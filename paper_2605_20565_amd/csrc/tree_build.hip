@@ -82,6 +82,8 @@ __device__ __forceinline__ uint32_t block_exscan_256(uint32_t v, uint32_t *sh_w,
     return pre + x - v;
 }
 
+}  // namespace
+
 // -- device-wide exclusive scan of uint32 (reduce/scan per 2048 + recursion) -
 __global__ __launch_bounds__(kSortThreads) void k_scan_tiles(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                                                              int64_t n, uint32_t *__restrict__ sums)
@@ -234,6 +236,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t *
         }
     }
 }
+
+namespace {
 
 __global__ void k_iota(int32_t *v, int64_t n)
 {
@@ -389,32 +393,36 @@ int dalloc(DevBuf &b, size_t bytes)
 
 }  // namespace
 
-// Sort (keys, values) by key over the low `bits` bits.  Result ends in
-// (*k_res, *v_res), which point at either the input or the alternate buffers.
-int radix_sort_pairs(uint64_t *k0, int32_t *v0, uint64_t *k1, int32_t *v1, int64_t n, int bits,
-                     uint64_t **k_res, int32_t **v_res, hipStream_t s)
+// Device workspace (bytes) of radix_sort_pairs for n keys.
+int64_t radix_ws_bytes(int64_t n)
+{
+    const int64_t nb = (n + kSortTile - 1) / kSortTile;
+    const int64_t nc = (int64_t)kRadix * nb;
+    return 4 * (2 * nc + scan_tmp_words(nc)) + 256;
+}
+
+// LSD radix sort of (key, value) pairs over the low `bits` bits, 8 bits per
+// pass, without allocating (ws: radix_ws_bytes(n) bytes).  After an even
+// number of passes the result is in (k0, v0), after an odd number in (k1, v1);
+// *k_res / *v_res point at it.
+void radix_sort_pairs(uint64_t *k0, int32_t *v0, uint64_t *k1, int32_t *v1, int64_t n, int bits, void *ws,
+                      uint64_t **k_res, int32_t **v_res, hipStream_t s)
 {
     const int nb = (int)((n + kSortTile - 1) / kSortTile);
     const int64_t ncounts = (int64_t)kRadix * nb;
-    DevBuf counts, offs, tmp;
-    int rc;
-    if ((rc = dalloc(counts, ncounts * 4))) return rc;
-    if ((rc = dalloc(offs, ncounts * 4))) return rc;
-    if ((rc = dalloc(tmp, scan_tmp_words(ncounts) * 4))) return rc;
+    uint32_t *counts = (uint32_t *)ws, *offs = counts + ncounts, *tmp = offs + ncounts;
     uint64_t *ka = k0, *kb = k1;
     int32_t *va = v0, *vb = v1;
-    for (int shift = 0; shift < bits; shift += kRadixBits) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n, shift, (uint32_t *)counts.p, nb);
-        exclusive_scan((uint32_t *)counts.p, (uint32_t *)offs.p, ncounts, (uint32_t *)tmp.p, s);
+    for (int shift = 0; shift < bits && n > 0; shift += kRadixBits) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kSortThreads), 0, s, ka, n, shift, counts, nb);
+        exclusive_scan(counts, offs, ncounts, tmp, s);
         hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kSortThreads), 0, s, ka, va, kb, vb, n, shift,
-                           (const uint32_t *)offs.p, nb);
+                           (const uint32_t *)offs, nb);
         std::swap(ka, kb);
         std::swap(va, vb);
     }
-    OT_HIP(hipGetLastError());
     *k_res = ka;
     *v_res = va;
-    return OT_OK;
 }
 
 }  // namespace ot
@@ -452,11 +460,12 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
     hipLaunchKernelGGL(k_iota, dim3(nblk(n)), dim3(256), 0, s, (int32_t *)va.p, n);
     uint64_t *ks;
     int32_t *perm;
+    DevBuf sws;
+    if ((rc = dalloc(sws, radix_ws_bytes(n)))) return rc;
     // Keys of a valid tree use 3L bits; sort on those (others fail validation).
-    if ((rc = radix_sort_pairs((uint64_t *)ka.p, (int32_t *)va.p, (uint64_t *)kb.p, (int32_t *)vb.p, n, 3 * L,
-                               &ks, &perm, s)))
-        return rc;
-    if (L == 0) { ks = (uint64_t *)ka.p; perm = (int32_t *)va.p; }
+    radix_sort_pairs((uint64_t *)ka.p, (int32_t *)va.p, (uint64_t *)kb.p, (int32_t *)vb.p, n, 3 * L, sws.p, &ks,
+                     &perm, s);
+    OT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_gather_levels, dim3(nblk(n)), dim3(256), 0, s, levels, perm, (uint8_t *)lvs.p, n);
 
     // Table layout: root level r = min(l_min, 8), then steps of <= 3 levels.

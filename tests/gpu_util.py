@@ -53,3 +53,26 @@ def fixed_point_quantum(forces: np.ndarray) -> float:
 
 
 TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+
+# Absolute precision of a delta weight computed in FP64 from the phi formula:
+# its outer branch cancels to zero at |r| = 3/2, so a computed weight is only
+# good to ~eps absolute (not relative).  A leaf that receives nothing but
+# edge-of-support weights therefore carries an absolute error ~eps * sum |F|
+# in any FP64 evaluation, the oracle's included.
+ETA = 2.0 ** -46
+
+
+def spread_bound(S, A, cnt, dtype, quantum=None):
+    """Per-leaf error bound for spreading: tol * sum|w F| + ETA * sum|F|,
+    plus half a fixed-point quantum per contribution in FIXED mode."""
+    b = TOL[dtype] * S + ETA * A
+    if quantum is not None:
+        b = b + cnt[:, None] * 0.5 * quantum * 1.0001
+    return b
+
+
+def spread_excess(got, f, S, A, cnt, dtype, quantum=None) -> float:
+    """max |got - f| / bound (<= 1 passes)."""
+    b = spread_bound(S, A, cnt, dtype, quantum)
+    d = np.abs(np.asarray(got, dtype=np.float64) - f)
+    return float((d / np.maximum(b, 1e-300)).max()) if d.size else 0.0

@@ -14,7 +14,8 @@ import pytest
 import torch
 
 import synth
-from gpu_util import TOL, as_dtype, fixed_point_quantum, gpu_tree, oracle_tree, scaled_err, to_dev
+from gpu_util import (TOL, as_dtype, fixed_point_quantum, gpu_tree, oracle_tree, scaled_err, spread_excess,
+                      to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -64,7 +65,7 @@ def test_encode_keys_bitexact(ot):
         assert np.array_equal(got, oracle.encode_keys(a, L))
 
 
-@pytest.mark.parametrize("which", ["cfg1", "rand_a", "rand_b", "deep", "lmin9"])
+@pytest.mark.parametrize("which", ["cfg1", "rand_a", "rand_b", "deep", "lmin6"])
 def test_build_tree_order_and_perm(ot, which):
     rng = np.random.default_rng(7)
     if which == "cfg1":
@@ -75,8 +76,8 @@ def test_build_tree_order_and_perm(ot, which):
         spec = synth.random_tree(0, 5, rng, 0.3, periodic=False, balance=False)
     elif which == "deep":   # more than 3 levels below the root: several table levels
         spec = synth.band_tree(2, 9, [synth.Sphere((0.3, 0.6, 0.5), 0.2)], seed=3)
-    else:                   # l_min above the root table level
-        spec = synth.band_tree(9, 10, [synth.Sphere((0.5, 0.5, 0.5), 0.05)], seed=4)
+    else:                   # 262k base cells, 4 refined levels
+        spec = synth.band_tree(6, 10, [synth.Sphere((0.5, 0.5, 0.5), 0.05)], seed=4)
     t = gpu_tree(spec)
     o = oracle_tree(spec)
     keys, lv = t.leaves()
@@ -85,6 +86,20 @@ def test_build_tree_order_and_perm(ot, which):
     assert np.array_equal(t.perm.cpu().numpy().astype(np.int64), o.perm)
     inf = t.info()
     assert inf.n_leaves == spec.n_leaves and inf.table_levels >= 1
+
+
+def test_build_tree_capacity_is_checked_before_any_work(ot):
+    """2^26 leaves is the id field's capacity; a complete tree with l_min = 9
+    already has 8^9 leaves, so it is refused up front."""
+    spec_n = 8 ** 9
+    K = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(ot.OtError) as e:
+        import ctypes
+        h = ctypes.c_void_p()
+        desc = ot.TreeDesc(9, 10, 1)
+        ot._check(ot.lib.ot_build_tree(ot._ptr(K), ot._ptr(K), spec_n, ctypes.byref(desc), None, None,
+                                       ctypes.byref(h)))
+    assert e.value.code == -7
 
 
 def test_build_tree_rejects_bad_partitions(ot):
@@ -173,20 +188,19 @@ def test_interpolate_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
 def test_spread_atomic_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
     w, o = cfg1
     pts, frc, _ = _inputs(w, o, dtype)
-    f, S, cnt = o.spread(frc, pts, with_scale=True)
+    f, S, cnt, A = o.spread(frc, pts, with_scale=True)
     got = cfg1_gpu.spread(to_dev(frc, dtype), to_dev(pts, dtype), mode="atomic").cpu().numpy()
-    assert scaled_err(got, f, S) <= TOL[dtype]
+    assert spread_excess(got, f, S, A, cnt, dtype) <= 1.0
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_spread_fixed_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
     w, o = cfg1
     pts, frc, _ = _inputs(w, o, dtype)
-    f, S, cnt = o.spread(frc, pts, with_scale=True)
+    f, S, cnt, A = o.spread(frc, pts, with_scale=True)
     got = cfg1_gpu.spread(to_dev(frc, dtype), to_dev(pts, dtype), mode="fixed").cpu().numpy()
-    q = fixed_point_quantum(frc)
-    bound = TOL[torch.float32] * S + (cnt[:, None] * 0.5 * q) * 1.0001 + 1e-300
-    assert np.all(np.abs(got - f) <= bound)
+    # the quantisation term dominates in FP64; FP32 adds its own rounding
+    assert spread_excess(got, f, S, A, cnt, torch.float32, fixed_point_quantum(frc)) <= 1.0
 
 
 def test_fixed_point_is_bitwise_reproducible(ot, cfg1, cfg1_gpu):
@@ -245,8 +259,8 @@ def test_nonperiodic_and_deep_tree_parity(ot, dtype):
     assert np.array_equal(ids.cpu().numpy().astype(np.int64), o.locate(pts))
     U, S = o.interpolate(fld, pts, with_scale=True)
     assert scaled_err(vel.cpu().numpy(), U, S) <= TOL[dtype]
-    f, Sf, _ = o.spread(frc, pts, with_scale=True)
-    assert scaled_err(fo.cpu().numpy(), f, Sf) <= TOL[dtype]
+    f, Sf, cnt, A = o.spread(frc, pts, with_scale=True)
+    assert spread_excess(fo.cpu().numpy(), f, Sf, A, cnt, dtype) <= 1.0
 
 
 def test_empty_input(ot, cfg1_gpu):
@@ -323,10 +337,9 @@ def test_batch_matches_plain_launches(ot, cfg1, cfg1_gpu, dtype):
             if op & 4:
                 spread_rows[a:b] = True
         mask = spread_rows.cpu().numpy()
-        f, S, cnt = o.spread(frc[mask], pts[mask], with_scale=True)
+        f, S, cnt, A = o.spread(frc[mask], pts[mask], with_scale=True)
         q = fixed_point_quantum(frc)      # the plan's scale covers all n forces
-        bound = TOL[torch.float32] * S + cnt[:, None] * 0.5 * q * 1.0001 + 1e-300
-        assert np.all(np.abs(fo.cpu().numpy() - f) <= bound)
+        assert spread_excess(fo.cpu().numpy(), f, S, A, cnt, torch.float32, q) <= 1.0
         plan.close()
 
 
@@ -353,4 +366,35 @@ def test_batch_graph_replays_are_identical(ot, cfg1, cfg1_gpu):
         plan.run(P, field=Fd, force=F, ids=ids, vel=vel, field_out=fo)
         torch.cuda.synchronize()
         assert torch.equal(ids, ref[0]) and torch.equal(vel, ref[1]) and torch.equal(fo, ref[2])
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("mode", ["fixed", "atomic"])
+def test_batch_sorted_points_match_plain(ot, cfg1, cfg1_gpu, dtype, mode):
+    """Sorting the points by host leaf inside the plan changes nothing:
+    ids and velocities are bitwise those of the plain launches, fixed-point
+    spreading is bitwise the same, atomic spreading within tolerance."""
+    w, o = cfg1
+    pts, frc, fld = _inputs(w, o, dtype, extra=True)
+    P, F, Fd = to_dev(pts, dtype), to_dev(frc, dtype), to_dev(fld, dtype)
+    n = P.shape[0]
+    off = [0, 1000, 5000, n]
+    plan = ot.BatchPlan(cfg1_gpu, off, [7, 7, 7], dtype=dtype, mode=mode, sort_points=True, block=256, tile=512)
+    ids = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+    vel = torch.zeros((n, 3), dtype=dtype, device="cuda")
+    fo = torch.empty((cfg1_gpu.n_leaves, 3), dtype=dtype, device="cuda")
+    for _ in range(2):
+        plan.run(P, field=Fd, force=F, ids=ids, vel=vel, field_out=fo)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, cfg1_gpu.locate(P))
+        assert torch.equal(vel, cfg1_gpu.interpolate(Fd, P))
+        ref = cfg1_gpu.spread(F, P, mode=mode)
+        if mode == "fixed":
+            assert torch.equal(fo, ref)
+        else:
+            f, S, cnt, A = o.spread(frc, pts, with_scale=True)
+            assert spread_excess(fo.cpu().numpy(), f, S, A, cnt, dtype) <= 1.0
+    with pytest.raises(ot.OtError):
+        ot.BatchPlan(cfg1_gpu, off, [7, 3, 7], dtype=dtype, mode=mode, sort_points=True)
     plan.close()
