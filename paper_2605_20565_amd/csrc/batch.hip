@@ -39,23 +39,24 @@ struct ot_batch_plan {
     hipEvent_t ev[2];
     // point sorting (OT_TUNE_SORT_POINTS)
     bool sort_points;
-    int sort_bits;
+    int sort_bits, sort_shift;
     int ops_all;              // the common ops of every instance
     uint64_t *skey[2];
     int32_t *sval[2];
     void *sws;                // radix sort workspace
-    void *spos, *sforce, *svel;
 };
 
 namespace ot {
 namespace {
 
 constexpr uint32_t kCountMask = 0x00FFFFFFu;
+constexpr int kSortKeyBits = 16;   // two radix passes
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__restrict__ tile_start,
                                                const uint32_t *__restrict__ tile_info, int64_t n_tiles,
-                                               unsigned *__restrict__ counter, const T *__restrict__ pos,
+                                               unsigned *__restrict__ counter, const int32_t *__restrict__ perm,
+                                               const T *__restrict__ pos,
                                                const T *__restrict__ field, const T *__restrict__ force,
                                                int32_t *__restrict__ ids, T *__restrict__ vel, T *__restrict__ fout,
                                                unsigned long long *__restrict__ facc, const FxState *__restrict__ fx)
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
         const int64_t end = start + (int64_t)(info & kCountMask);
         switch (info >> 24) {
 #define OT_CASE(OPSV) \
-    case OPSV: track_range<T, OPSV>(tv, start, end, pos, field, force, ids, vel, sink); break;
+    case OPSV: track_range<T, OPSV>(tv, start, end, perm, pos, field, force, ids, vel, sink); break;
             OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
 #undef OT_CASE
         default: break;
@@ -90,11 +91,13 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
     sink.flush();
 }
 
-// Sort keys: host leaf id (n_leaves for points without a host, so they
-// sort last); values: the point's index.  Writes ids when asked.
+// Sort keys: host leaf id >> shift (n_leaves for points without a host, so
+// they sort last): points end up grouped in runs of 2^shift consecutive
+// leaves, enough for cache and table locality.  Values: the point's index.
+// Writes ids when asked.
 template <typename T>
 __global__ void k_sort_keys(TreeView tv, int64_t n, const T *__restrict__ pos, int32_t *__restrict__ ids,
-                            uint64_t *__restrict__ keys, int32_t *__restrict__ vals, uint32_t none)
+                            uint64_t *__restrict__ keys, int32_t *__restrict__ vals, uint32_t none, int shift)
 {
     const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (k >= n) return;
@@ -102,32 +105,8 @@ __global__ void k_sort_keys(TreeView tv, int64_t n, const T *__restrict__ pos, i
     const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
     const uint32_t host = ok ? (descend(tv, I[0], I[1], I[2]) & kIdMask) : none;
     if (ids) ids[k] = ok ? (int32_t)host : -1;
-    keys[k] = host;
+    keys[k] = host >> shift;
     vals[k] = (int32_t)k;
-}
-
-template <typename T>
-__global__ void k_gather_rows(const int32_t *__restrict__ perm, const T *__restrict__ src, T *__restrict__ dst,
-                              int64_t n)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t j = 3 * (int64_t)perm[i];
-    dst[3 * i] = src[j];
-    dst[3 * i + 1] = src[j + 1];
-    dst[3 * i + 2] = src[j + 2];
-}
-
-template <typename T>
-__global__ void k_scatter_rows(const int32_t *__restrict__ perm, const T *__restrict__ src, T *__restrict__ dst,
-                               int64_t n)
-{
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t j = 3 * (int64_t)perm[i];
-    dst[j] = src[3 * i];
-    dst[j + 1] = src[3 * i + 1];
-    dst[j + 2] = src[3 * i + 2];
 }
 
 template <typename T, int MODE>
@@ -140,36 +119,25 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
     int rc;
     if (p->ops_union & kOpSpread)
         if ((rc = spread_prologue(t, p->dtype, p->mode, 0, force, n, fout, s))) return rc;
-    const T *kpos = (const T *)pos, *kforce = (const T *)force;
-    T *kvel = (T *)vel;
-    int32_t *kids = ids;
     const int32_t *perm = nullptr;
+    int32_t *kids = ids;
     if (p->sort_points && n > 0) {
         const unsigned gb = (unsigned)((n + 255) / 256);
         hipLaunchKernelGGL(k_sort_keys<T>, dim3(gb), dim3(256), 0, s, t->view, n, (const T *)pos,
                            (p->ops_all & kOpLocate) ? ids : (int32_t *)nullptr, p->skey[0], p->sval[0],
-                           (uint32_t)t->n_leaves);
+                           (uint32_t)t->n_leaves, p->sort_shift);
         uint64_t *kr;
         int32_t *vr;
         radix_sort_pairs(p->skey[0], p->sval[0], p->skey[1], p->sval[1], n, p->sort_bits, p->sws, &kr, &vr, s);
         perm = vr;
-        hipLaunchKernelGGL(k_gather_rows<T>, dim3(gb), dim3(256), 0, s, perm, (const T *)pos, (T *)p->spos, n);
-        if (p->ops_all & kOpSpread)
-            hipLaunchKernelGGL(k_gather_rows<T>, dim3(gb), dim3(256), 0, s, perm, (const T *)force, (T *)p->sforce, n);
-        kpos = (const T *)p->spos;
-        kforce = (const T *)p->sforce;
-        kvel = (T *)p->svel;
         kids = nullptr;
     }
     if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
     hipLaunchKernelGGL((k_batch<T, MODE>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start, p->tile_info,
-                       p->n_tiles, p->counter, kpos, (const T *)field, kforce, kids, kvel, (T *)fout, t->fx_acc,
-                       (const FxState *)t->scratch);
+                       p->n_tiles, p->counter, perm, (const T *)pos, (const T *)field, (const T *)force, kids,
+                       (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
     OT_HIP(hipGetLastError());
     if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
-    if (perm && (p->ops_all & kOpInterp))
-        hipLaunchKernelGGL(k_scatter_rows<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, perm,
-                           (const T *)p->svel, (T *)vel, n);
     if (p->ops_union & kOpSpread)
         if ((rc = spread_epilogue(t, p->dtype, p->mode, 0, fout, s))) return rc;
     OT_HIP(hipGetLastError());
@@ -259,17 +227,15 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
         const int64_t n = p->n_points;
         int bits = 1;
         while ((int64_t(1) << bits) <= tree->n_leaves) ++bits;   // keys go up to n_leaves
-        p->sort_bits = bits;
-        const size_t row = (dtype == OT_F32 ? 4 : 8) * 3 * (size_t)n;
+        p->sort_shift = std::max(0, bits - kSortKeyBits);
+        p->sort_bits = bits - p->sort_shift;
         hipError_t e = hipSuccess;
         if (e == hipSuccess) e = hipMalloc((void **)&p->skey[0], 8 * (size_t)n);
         if (e == hipSuccess) e = hipMalloc((void **)&p->skey[1], 8 * (size_t)n);
         if (e == hipSuccess) e = hipMalloc((void **)&p->sval[0], 4 * (size_t)n);
         if (e == hipSuccess) e = hipMalloc((void **)&p->sval[1], 4 * (size_t)n);
         if (e == hipSuccess) e = hipMalloc(&p->sws, (size_t)radix_ws_bytes(n));
-        if (e == hipSuccess) e = hipMalloc(&p->spos, row);
-        if (e == hipSuccess && (ops_all & kOpSpread)) e = hipMalloc(&p->sforce, row);
-        if (e == hipSuccess && (ops_all & kOpInterp)) e = hipMalloc(&p->svel, row);
+
         if (e != hipSuccess) {
             (void)hipGetLastError();
             ot_batch_plan_destroy(p);
@@ -393,8 +359,7 @@ extern "C" int ot_batch_plan_destroy(ot_batch_plan *p)
     drop_graph(p);
     if (p->ev[0]) (void)hipEventDestroy(p->ev[0]);
     if (p->ev[1]) (void)hipEventDestroy(p->ev[1]);
-    for (void *q : {(void *)p->skey[0], (void *)p->skey[1], (void *)p->sval[0], (void *)p->sval[1], p->sws, p->spos,
-                    p->sforce, p->svel})
+    for (void *q : {(void *)p->skey[0], (void *)p->skey[1], (void *)p->sval[0], (void *)p->sval[1], p->sws})
         if (q) (void)hipFree(q);
     if (p->tile_start) (void)hipFree(p->tile_start);
     if (p->tile_info) (void)hipFree(p->tile_info);

@@ -37,11 +37,11 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
         LdsSink<T, MODE, S> sink{keys, vals, &used, fout, facc, scale};
         sink.clear();
         __syncthreads();
-        track_range<T, OPS>(tv, start, end, pos, field, force, ids, vel, sink);
+        track_range<T, OPS>(tv, start, end, nullptr, pos, field, force, ids, vel, sink);
         sink.flush();
     } else {
         DirectSink<T, MODE> sink{fout, facc, 0.0};
-        track_range<T, OPS>(tv, start, end, pos, field, force, ids, vel, sink);
+        track_range<T, OPS>(tv, start, end, nullptr, pos, field, force, ids, vel, sink);
     }
 }
 
@@ -102,7 +102,7 @@ int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &fx->maxbits, (int64_t)1, 0ull);
         const int64_t m = n * 3;
         if (m > 0) {
-            unsigned gb = (unsigned)std::min<int64_t>((m + 255) / 256, 2048);
+            unsigned gb = (unsigned)std::min<int64_t>((m + 1023) / 1024, 16384);
             if (dtype == OT_F32)
                 hipLaunchKernelGGL(k_maxabs<float>, dim3(gb), dim3(256), 0, s, (const float *)force, m, &fx->maxbits);
             else

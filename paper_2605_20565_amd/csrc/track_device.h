@@ -76,6 +76,7 @@ __device__ __forceinline__ void make_stencil(const TreeView &tv, const T X[3], c
             bool ok = true;
             if (tv.periodic) nn &= (Ml - 1);
             else ok = (nn >= 0) && (nn < Ml);
+            if (!ok) nn = 0;   // dropped node: keep its coordinates inside the domain
             const uint32_t Nc = ((uint32_t)nn << sh) | half;
             st.N[d][o] = Nc;
             st.R[d][o] = part1by2(Nc >> rs);
@@ -100,11 +101,22 @@ struct AccType { using type = T; };
 template <typename T>
 struct AccType<T, kModeFixed> { using type = unsigned long long; };
 
-template <typename T, int MODE>
-__device__ __forceinline__ typename AccType<T, MODE>::type to_acc(T v, double scale)
+// Fixed point: q = rint(w F 2^s) with w F formed exactly in FP64 for FP32
+// inputs (a 24 x 24-bit product fits 53 bits) and in FP64 arithmetic for
+// FP64 inputs; |w F 2^s| <= 2^51 by the choice of s, so adding 1.5 * 2^52
+// rounds to the nearest integer (ties to even) and leaves it, in two's
+// complement, in the low mantissa bits.
+__device__ __forceinline__ unsigned long long fx_round(double x)
 {
-    if constexpr (MODE == kModeFixed) return (unsigned long long)__double2ll_rn((double)v * scale);
-    else return v;
+    const double magic = 6755399441055744.0;   // 1.5 * 2^52
+    return (unsigned long long)(__double_as_longlong(x + magic) - __double_as_longlong(magic));
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ typename AccType<T, MODE>::type to_acc(T w, T f, double scale)
+{
+    if constexpr (MODE == kModeFixed) return fx_round((double)w * ((double)f * scale));
+    else return w * f;
 }
 
 template <typename T, int MODE>
@@ -125,7 +137,7 @@ struct DirectSink {
     {
         const int64_t j = 3 * (int64_t)leaf;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) global_add<T, MODE>(fout, facc, j + c, to_acc<T, MODE>(w * F[c], scale));
+        for (int c = 0; c < 3; ++c) global_add<T, MODE>(fout, facc, j + c, to_acc<T, MODE>(w, F[c], scale));
     }
 };
 
@@ -162,9 +174,9 @@ struct LdsSink {
     {
         const uint32_t key = leaf + 1u;
         uint32_t slot = leaf & (S - 1);
-        const Acc a0 = to_acc<T, MODE>(w * F[0], scale);
-        const Acc a1 = to_acc<T, MODE>(w * F[1], scale);
-        const Acc a2 = to_acc<T, MODE>(w * F[2], scale);
+        const Acc a0 = to_acc<T, MODE>(w, F[0], scale);
+        const Acc a1 = to_acc<T, MODE>(w, F[1], scale);
+        const Acc a2 = to_acc<T, MODE>(w, F[2], scale);
 #pragma unroll 1
         for (int p = 0; p < kProbe; ++p) {
             uint32_t cur = keys[slot];
@@ -220,55 +232,77 @@ struct LdsSink {
     }
 };
 
+// One point.  The 27 node lookups are issued together, then the 27 field
+// gathers, then the spreading, so each phase's loads overlap.  k indexes the
+// point's data through perm when given (sorted processing); ids are written
+// at the data index.
 template <typename T, int OPS, typename Sink>
-__device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const T *__restrict__ pos,
-                                            const T *__restrict__ field, const T *__restrict__ force,
-                                            int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink)
+__device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const int32_t *__restrict__ perm,
+                                            const T *__restrict__ pos, const T *__restrict__ field,
+                                            const T *__restrict__ force, int32_t *__restrict__ ids,
+                                            T *__restrict__ vel, Sink &sink)
 {
-    const T X[3] = {pos[3 * k], pos[3 * k + 1], pos[3 * k + 2]};
+    const int64_t kd = perm ? (int64_t)perm[k] : k;
+    const T X[3] = {pos[3 * kd], pos[3 * kd + 1], pos[3 * kd + 2]};
     uint32_t I[3];
     const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
     const uint32_t e = ok ? descend(tv, I[0], I[1], I[2]) : 0u;
-    if (OPS & kOpLocate) ids[k] = ok ? (int32_t)(e & kIdMask) : -1;
+    if (OPS & kOpLocate) ids[kd] = ok ? (int32_t)(e & kIdMask) : -1;
     if (!(OPS & (kOpInterp | kOpSpread))) return;
 
     T U[3] = {T(0), T(0), T(0)};
     if (ok) {
         Stencil<T> st;
         make_stencil<T>(tv, X, I, e, st);
-        T F[3] = {T(0), T(0), T(0)};
-        if (OPS & kOpSpread) {
-            F[0] = force[3 * k];
-            F[1] = force[3 * k + 1];
-            F[2] = force[3 * k + 2];
+        // phase 1: root-table entries of the 27 nodes (independent loads);
+        // nodes dropped at a non-periodic wall are not looked up
+        uint32_t ent[27];
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+            const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
+            if (q == 13) ent[q] = st.host | ((uint32_t)st.level << kLevelShift);
+            else if ((st.valid & need) != need) ent[q] = 0u;
+            else ent[q] = __ldg(tv.table + (st.R[0][ox] | (st.R[1][oy] << 1) | (st.R[2][oz] << 2)));
         }
+        // phase 2: nodes inside split root cells continue the descent (rare)
 #pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
+        for (int q = 0; q < 27; ++q) {
+            if (ent[q] & kSplit) {
+                const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+                ent[q] = descend_below_root(tv, ent[q], st.N[0][ox], st.N[1][oy], st.N[2][oz]);
+            }
+        }
+        // phase 3: interpolation gathers
+        if (OPS & kOpInterp) {
 #pragma unroll
-            for (int oy = 0; oy < 3; ++oy) {
-                const T wyz = st.w[1][oy] * st.w[2][oz];
+            for (int q = 0; q < 27; ++q) {
+                const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+                const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
+                if ((st.valid & need) != need) continue;
+                const int64_t j = 3 * (int64_t)(ent[q] & kIdMask);
+                const T w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
+                U[0] += w * field[j];
+                U[1] += w * field[j + 1];
+                U[2] += w * field[j + 2];
+            }
+        }
+        // phase 4: spreading
+        if (OPS & kOpSpread) {
+            const T F[3] = {force[3 * kd], force[3 * kd + 1], force[3 * kd + 2]};
 #pragma unroll
-                for (int ox = 0; ox < 3; ++ox) {
-                    const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
-                    if ((st.valid & need) != need) continue;
-                    // the centre node lies in the host leaf
-                    const uint32_t leaf = (ox == 1 && oy == 1 && oz == 1) ? st.host : node_leaf<T>(tv, st, ox, oy, oz);
-                    const T w = st.w[0][ox] * wyz;
-                    if (OPS & kOpInterp) {
-                        const int64_t j = 3 * (int64_t)leaf;
-                        U[0] += w * field[j];
-                        U[1] += w * field[j + 1];
-                        U[2] += w * field[j + 2];
-                    }
-                    if (OPS & kOpSpread) sink.add(leaf, w, F);
-                }
+            for (int q = 0; q < 27; ++q) {
+                const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+                const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
+                if ((st.valid & need) != need) continue;
+                sink.add(ent[q] & kIdMask, st.w[0][ox] * st.w[1][oy] * st.w[2][oz], F);
             }
         }
     }
     if (OPS & kOpInterp) {
-        vel[3 * k] = U[0];
-        vel[3 * k + 1] = U[1];
-        vel[3 * k + 2] = U[2];
+        vel[3 * kd] = U[0];
+        vel[3 * kd + 1] = U[1];
+        vel[3 * kd + 2] = U[2];
     }
 }
 
@@ -358,8 +392,9 @@ __device__ __forceinline__ double bits_value<float>(unsigned long long b) { retu
 template <>
 __device__ __forceinline__ double bits_value<double>(unsigned long long b) { return __longlong_as_double((long long)b); }
 
-// s = 62 - E with n max|F| <= 2^E: every leaf sum stays below 2^62 in
-// magnitude (weights are >= 0 and one point's weights sum to 1).
+// s = min(62 - E, 51 - Ef) with n max|F| <= 2^E and max|F| <= 2^Ef: every
+// leaf sum stays below 2^62 in magnitude (weights are >= 0 and one point's
+// weights sum to 1) and every single contribution below 2^51.
 template <typename T>
 __global__ void k_fx_prepare(FxState *fx, int64_t n)
 {
@@ -367,9 +402,10 @@ __global__ void k_fx_prepare(FxState *fx, int64_t n)
     const double mf = bits_value<T>(fx->maxbits);
     int s = 0;
     if (mf > 0.0 && n > 0) {
-        int E;
+        int E, Ef;
         (void)frexp((double)n * mf, &E);
-        s = 62 - E;
+        (void)frexp(mf, &Ef);
+        s = min(62 - E, 51 - Ef);
     }
     fx->scale = ldexp(1.0, s);
     fx->inv = ldexp(1.0, -s);
@@ -388,12 +424,13 @@ __global__ void k_fx_finalize(const unsigned long long *__restrict__ acc, T *__r
 
 // Process points [start, end) of one tile with all threads of the workgroup.
 template <typename T, int OPS, typename Sink>
-__device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, int64_t end, const T *__restrict__ pos,
+__device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, int64_t end,
+                                            const int32_t *__restrict__ perm, const T *__restrict__ pos,
                                             const T *__restrict__ field, const T *__restrict__ force,
                                             int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink)
 {
     for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x)
-        track_point<T, OPS, Sink>(tv, k, pos, field, force, ids, vel, sink);
+        track_point<T, OPS, Sink>(tv, k, perm, pos, field, force, ids, vel, sink);
 }
 
 // LDS table size of the aggregating sink, per precision and mode

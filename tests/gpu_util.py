@@ -43,13 +43,15 @@ def scaled_err(got: np.ndarray, want: np.ndarray, scale: np.ndarray) -> float:
 
 
 def fixed_point_quantum(forces: np.ndarray) -> float:
-    """2^-s of the fixed-point spreading: s = 62 - E, 2^E >= n max|F|."""
+    """2^-s of the fixed-point spreading: s = min(62 - E, 51 - Ef),
+    2^E >= n max|F|, 2^Ef >= max|F|."""
     n = forces.shape[0]
     m = float(np.abs(forces[np.isfinite(forces)]).max()) if forces.size else 0.0
     if m == 0.0 or n == 0:
         return 1.0
     _, E = math.frexp(n * m)
-    return math.ldexp(1.0, -(62 - E))
+    _, Ef = math.frexp(m)
+    return math.ldexp(1.0, -min(62 - E, 51 - Ef))
 
 
 TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
