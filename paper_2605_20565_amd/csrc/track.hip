@@ -102,7 +102,7 @@ int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &fx->maxbits, (int64_t)1, 0ull);
         const int64_t m = n * 3;
         if (m > 0) {
-            unsigned gb = (unsigned)std::min<int64_t>((m + 1023) / 1024, 16384);
+            unsigned gb = (unsigned)std::min<int64_t>((m + 1023) / 1024, 1024);
             if (dtype == OT_F32)
                 hipLaunchKernelGGL(k_maxabs<float>, dim3(gb), dim3(256), 0, s, (const float *)force, m, &fx->maxbits);
             else

@@ -142,12 +142,15 @@ struct DirectSink {
 };
 
 // Workgroup-local aggregation: an open-addressing table in LDS keyed by leaf
-// id (slot = id mod S, linear probing) accumulates the contributions of all
-// points the workgroup handles; flush() adds each occupied slot to device
-// memory once.  Slots follow the ids, so the flush's atomics come in runs of
-// neighbouring addresses.  A contribution that finds no slot within kProbe
-// steps goes straight to device memory.  In FIXED mode every value is the
-// same rounded integer either way, so the result does not depend on the path.
+// id accumulates the contributions of all points the workgroup handles;
+// flush() adds each occupied slot to device memory once.  The first probe is
+// slot = id mod S, so the flush's atomics come in runs of neighbouring
+// addresses; on a collision the probe moves by an odd stride hashed from the
+// id (double hashing), because a workgroup's ids come in runs of consecutive
+// Morton ranks that would otherwise pile up into long occupied clusters.  A
+// contribution that finds no slot within kProbe steps goes straight to
+// device memory.  In FIXED mode every value is the same rounded integer
+// either way, so the result does not depend on the path.
 template <typename T, int MODE, int S>
 struct LdsSink {
     using Acc = typename AccType<T, MODE>::type;
@@ -173,10 +176,13 @@ struct LdsSink {
     __device__ __forceinline__ void add(uint32_t leaf, T w, const T F[3])
     {
         const uint32_t key = leaf + 1u;
-        uint32_t slot = leaf & (S - 1);
+        const uint32_t step = ((leaf * 0x9E3779B1u) >> 16) | 1u;
         const Acc a0 = to_acc<T, MODE>(w, F[0], scale);
         const Acc a1 = to_acc<T, MODE>(w, F[1], scale);
         const Acc a2 = to_acc<T, MODE>(w, F[2], scale);
+        // find (or claim) the slot; the adds follow once the lanes reconverge
+        uint32_t slot = leaf & (S - 1);
+        bool found = false;
 #pragma unroll 1
         for (int p = 0; p < kProbe; ++p) {
             uint32_t cur = keys[slot];
@@ -188,17 +194,21 @@ struct LdsSink {
                 }
             }
             if (cur == key) {
-                atomicAdd(&vals[3 * slot], a0);
-                atomicAdd(&vals[3 * slot + 1], a1);
-                atomicAdd(&vals[3 * slot + 2], a2);
-                return;
+                found = true;
+                break;
             }
-            slot = (slot + 1u) & (S - 1);
+            slot = (slot + step) & (S - 1);
         }
-        const int64_t j = 3 * (int64_t)leaf;
-        global_add<T, MODE>(fout, facc, j, a0);
-        global_add<T, MODE>(fout, facc, j + 1, a1);
-        global_add<T, MODE>(fout, facc, j + 2, a2);
+        if (found) {
+            atomicAdd(&vals[3 * slot], a0);
+            atomicAdd(&vals[3 * slot + 1], a1);
+            atomicAdd(&vals[3 * slot + 2], a2);
+        } else {
+            const int64_t j = 3 * (int64_t)leaf;
+            global_add<T, MODE>(fout, facc, j, a0);
+            global_add<T, MODE>(fout, facc, j + 1, a1);
+            global_add<T, MODE>(fout, facc, j + 2, a2);
+        }
     }
 
     // All threads of the workgroup; leaves the table empty.
@@ -228,7 +238,7 @@ struct LdsSink {
     {
         __syncthreads();
         const uint32_t u = *used;
-        if (u > (uint32_t)(S * 3 / 8)) flush();
+        if (u > (uint32_t)(S / 2)) flush();
     }
 };
 
@@ -372,9 +382,11 @@ __device__ __forceinline__ unsigned long long abs_bits(double v)
 
 // max |F| over finite components (bit patterns of non-negative IEEE values
 // order like the values, so an integer max is exact and order independent).
+// One atomic per workgroup: same-address atomics serialise.
 template <typename T>
-__global__ void k_maxabs(const T *__restrict__ f, int64_t m, unsigned long long *__restrict__ out)
+__global__ __launch_bounds__(256) void k_maxabs(const T *__restrict__ f, int64_t m, unsigned long long *__restrict__ out)
 {
+    __shared__ unsigned long long wmax[4];
     unsigned long long best = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         const T v = f[i];
@@ -382,7 +394,12 @@ __global__ void k_maxabs(const T *__restrict__ f, int64_t m, unsigned long long 
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) best = std::max(best, (unsigned long long)__shfl_xor(best, o, 64));
-    if ((threadIdx.x & 63) == 0 && best) atomicMax(out, best);
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) best = std::max(best, wmax[w]);
+        if (best) atomicMax(out, best);
+    }
 }
 
 template <typename T>
