@@ -182,6 +182,8 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     if (tile < block || tile % block || tile > (int)kCountMask) return fail(OT_ERR_INVALID, "tile must be a multiple of block");
     if (offsets[0] != 0) return fail(OT_ERR_INVALID, "offsets[0] must be 0");
     const bool sort_points = tuning && (tuning->flags & OT_TUNE_SORT_POINTS);
+    if (sort_points && offsets[n_inst] > (int64_t)INT32_MAX)
+        return fail(OT_ERR_CAPACITY, "point sorting indexes points with int32: at most 2^31 - 1 points");
     std::vector<int64_t> starts;
     std::vector<uint32_t> infos;
     int ops_union = 0, ops_all = -1;

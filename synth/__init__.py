@@ -176,7 +176,12 @@ def _leaves_only(refined: dict, l_min: int, l_max: int):
         if l < l_max:
             r = refined.get(l, np.empty(0, dtype=np.int64))
             if r.size:
-                cells = cells[~np.isin(cells, r, assume_unique=True)]
+                if l == l_min:
+                    keep = np.ones(m ** 3, dtype=bool)
+                    keep[r] = False
+                    cells = np.nonzero(keep)[0]
+                else:
+                    cells = cells[~np.isin(cells, r, assume_unique=True)]
         if cells.size == 0:
             continue
         x, y, z = _unlin(cells, m)
