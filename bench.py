@@ -39,6 +39,39 @@ BYTES_PER_POINT = {"f32": 12 + 4 + 12 + 12, "f64": 24 + 4 + 24 + 24}
 BYTES_PER_LEAF = {"f32": 9 + 12 + 12, "f64": 9 + 24 + 24}
 
 
+COPY_BYTES = 1 << 30
+
+
+def write_traffic(args, fetch_csv, write_csv):
+    """Per-launch HBM bytes of k_batch from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the same counter reads for the 1 GiB
+    calibration copy (which reads and writes exactly COPY_BYTES)."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        batch = [float(r["Counter_Value"]) for r in rows if "k_batch" in r["Kernel_Name"]]
+        copies = [float(r["Counter_Value"]) for r in rows if "copy" in r["Kernel_Name"].lower()]
+        if not batch or not copies:
+            raise SystemExit(f"{path}: no k_batch or copy dispatch with {counter}")
+        return sum(batch) / len(batch), max(copies)
+
+    fb, fc = per_kernel(fetch_csv, "FETCH_SIZE")
+    wb, wc = per_kernel(write_csv, "WRITE_SIZE")
+    ff = (COPY_BYTES / 1024.0) / fc
+    fw = (COPY_BYTES / 1024.0) / wc
+    rec = {"kernel": "k_batch", "config": args.config, "dtype": args.dtype, "mode": args.mode,
+           "kernel_hash": kernel_source_hash(),
+           "fetch_kib_per_launch": fb, "write_kib_per_launch": wb,
+           "copy_fetch_kib": fc, "copy_write_kib": wc, "factor_fetch": ff, "factor_write": fw,
+           "fetch_bytes": fb * 1024 * ff, "write_bytes": wb * 1024 * fw,
+           "bytes_per_launch": int(fb * 1024 * ff + wb * 1024 * fw)}
+    os.makedirs(os.path.dirname(PROFILE_TRAFFIC), exist_ok=True)
+    with open(PROFILE_TRAFFIC, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -79,13 +112,23 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-sort", action="store_true", help="process points in input order (no in-step sort)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use --block/--tile/--grid)")
+    ap.add_argument("--presort-shift", type=int, default=0,
+                    help="with --presorted: order by host id >> shift (6 mimics the in-step binning)")
     ap.add_argument("--presorted", action="store_true",
                     help="store the points in host-leaf order before timing (the layout a simulation that keeps "
                          "its particles sorted maintains) and run without the in-step sort")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="points in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip side measurements")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one 1 GiB device copy (reference kernel for rocprofv3 byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU: turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-calibration run into the per-launch traffic record under profiles/")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(args, *args.traffic_from)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -122,7 +165,7 @@ def main():
     force = torch.from_numpy(w.forces).to(dev, dt)
     field = tree.permute_rows(torch.from_numpy(w.field).to(dev, dt))
     if args.presorted:
-        order = torch.argsort(tree.locate(pos).long())
+        order = torch.argsort(tree.locate(pos).long() >> args.presort_shift, stable=True)
         pos, force = pos[order].contiguous(), force[order].contiguous()
         args.no_sort = True
     n = pos.shape[0]
@@ -213,6 +256,13 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     out.update(extra)
     out["build_tree_ms"] = round(build_ms, 2)
+    if args.copy_calibration:
+        a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     if tune_ms is not None:
         out["tuning_ms_per_step"] = tune_ms
     out["kernel_source"] = kernel_source_hash()

@@ -19,6 +19,9 @@ ARCH = os.environ.get("OT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
+    # no implicit multiply-add contraction: every instantiation of the per-point code
+    # (plain, fused, batched) rounds the same way; the fused ops it wants are written out
+    "-ffp-contract=off",
     # no packed-FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",

@@ -52,7 +52,7 @@ namespace {
 constexpr uint32_t kCountMask = 0x00FFFFFFu;
 constexpr int kSortKeyBits = 16;   // two radix passes
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool PER>
 __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__restrict__ tile_start,
                                                const uint32_t *__restrict__ tile_info, int64_t n_tiles,
                                                unsigned *__restrict__ counter, const int32_t *__restrict__ perm,
@@ -65,10 +65,9 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
     using Acc = typename AccType<T, MODE>::type;
     __shared__ uint32_t keys[S];
     __shared__ Acc vals[3 * S];
-    __shared__ uint32_t used;
     __shared__ unsigned s_tile;
     const double scale = MODE == kModeFixed ? fx->scale : 0.0;
-    LdsSink<T, MODE, S> sink{keys, vals, &used, fout, facc, scale};
+    LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
     sink.clear();
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
@@ -81,14 +80,13 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
         const int64_t end = start + (int64_t)(info & kCountMask);
         switch (info >> 24) {
 #define OT_CASE(OPSV) \
-    case OPSV: track_range<T, OPSV>(tv, start, end, perm, pos, field, force, ids, vel, sink); break;
+    case OPSV: track_range<T, OPSV, PER>(tv, start, end, perm, pos, field, force, ids, vel, sink); break;
             OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
 #undef OT_CASE
         default: break;
         }
-        sink.maybe_flush();
+        sink.flush();   // one spatially coherent tile per table fill
     }
-    sink.flush();
 }
 
 // Sort keys: host leaf id >> shift (n_leaves for points without a host, so
@@ -133,9 +131,14 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
         kids = nullptr;
     }
     if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
-    hipLaunchKernelGGL((k_batch<T, MODE>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start, p->tile_info,
-                       p->n_tiles, p->counter, perm, (const T *)pos, (const T *)field, (const T *)force, kids,
-                       (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+    if (t->view.periodic)
+        hipLaunchKernelGGL((k_batch<T, MODE, true>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start,
+                           p->tile_info, p->n_tiles, p->counter, perm, (const T *)pos, (const T *)field,
+                           (const T *)force, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+    else
+        hipLaunchKernelGGL((k_batch<T, MODE, false>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start,
+                           p->tile_info, p->n_tiles, p->counter, perm, (const T *)pos, (const T *)field,
+                           (const T *)force, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
     OT_HIP(hipGetLastError());
     if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
     if (p->ops_union & kOpSpread)
@@ -248,10 +251,10 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per_cu = 0;
-    const void *kfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? (const void *)k_batch<float, kModeFixed>
-                                                                 : (const void *)k_batch<float, kModeAtomic>)
-                                      : (mode == OT_SPREAD_FIXED ? (const void *)k_batch<double, kModeFixed>
-                                                                 : (const void *)k_batch<double, kModeAtomic>);
+    const void *kfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? (const void *)k_batch<float, kModeFixed, true>
+                                                                 : (const void *)k_batch<float, kModeAtomic, true>)
+                                      : (mode == OT_SPREAD_FIXED ? (const void *)k_batch<double, kModeFixed, true>
+                                                                 : (const void *)k_batch<double, kModeAtomic, true>);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, block, 0);
     if (per_cu <= 0) per_cu = 1;
     int grid = tuning && tuning->grid ? tuning->grid : std::max(1, cus) * per_cu;

@@ -18,7 +18,7 @@ namespace {
 
 // One workgroup per tile of `tile` consecutive points.  Spreading goes
 // through the workgroup's LDS aggregation table, flushed once at the end.
-template <typename T, int OPS, int MODE>
+template <typename T, int OPS, int MODE, bool PER>
 __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t tile, const T *__restrict__ pos,
                                                const T *__restrict__ field, const T *__restrict__ force,
                                                int32_t *__restrict__ ids, T *__restrict__ vel,
@@ -32,16 +32,15 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
         using Acc = typename AccType<T, MODE>::type;
         __shared__ uint32_t keys[S];
         __shared__ Acc vals[3 * S];
-        __shared__ uint32_t used;
         const double scale = MODE == kModeFixed ? fx->scale : 0.0;
-        LdsSink<T, MODE, S> sink{keys, vals, &used, fout, facc, scale};
+        LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
         sink.clear();
         __syncthreads();
-        track_range<T, OPS>(tv, start, end, nullptr, pos, field, force, ids, vel, sink);
+        track_range<T, OPS, PER>(tv, start, end, nullptr, pos, field, force, ids, vel, sink);
         sink.flush();
     } else {
         DirectSink<T, MODE> sink{fout, facc, 0.0};
-        track_range<T, OPS>(tv, start, end, nullptr, pos, field, force, ids, vel, sink);
+        track_range<T, OPS, PER>(tv, start, end, nullptr, pos, field, force, ids, vel, sink);
     }
 }
 
@@ -65,9 +64,13 @@ int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, hipStream_t s, int64
     T *V = (T *)vel, *O = (T *)fout;
     const FxState *fx = (const FxState *)t->scratch;
     const int64_t tile = (int64_t)b.x * kPointsPerThread;
-#define OT_LAUNCH(OPSV)                                                                                        \
-    hipLaunchKernelGGL((k_track<T, OPSV, MODE>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O, t->fx_acc, \
-                       fx);                                                                                    \
+#define OT_LAUNCH(OPSV)                                                                                         \
+    if (t->view.periodic)                                                                                        \
+        hipLaunchKernelGGL((k_track<T, OPSV, MODE, true>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,    \
+                           t->fx_acc, fx);                                                                       \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_track<T, OPSV, MODE, false>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,   \
+                           t->fx_acc, fx);                                                                       \
     break;
     switch (ops) {
     case 1: OT_LAUNCH(1)

@@ -52,7 +52,7 @@ struct Stencil {
     uint32_t host;
 };
 
-template <typename T>
+template <typename T, bool PER>
 __device__ __forceinline__ void make_stencil(const TreeView &tv, const T X[3], const uint32_t I[3], uint32_t e,
                                              Stencil<T> &st)
 {
@@ -74,7 +74,7 @@ __device__ __forceinline__ void make_stencil(const TreeView &tv, const T X[3], c
         for (int o = 0; o < 3; ++o) {
             int32_t nn = c + o - 1;
             bool ok = true;
-            if (tv.periodic) nn &= (Ml - 1);
+            if (PER) nn &= (Ml - 1);
             else ok = (nn >= 0) && (nn < Ml);
             if (!ok) nn = 0;   // dropped node: keep its coordinates inside the domain
             const uint32_t Nc = ((uint32_t)nn << sh) | half;
@@ -157,7 +157,6 @@ struct LdsSink {
     static constexpr int kProbe = 8;
     uint32_t *keys;     // S, 0 = empty, else leaf + 1
     Acc *vals;          // 3 S
-    uint32_t *used;     // occupied slots
     T *fout;
     unsigned long long *facc;
     double scale;
@@ -170,34 +169,37 @@ struct LdsSink {
             vals[3 * i + 1] = Acc(0);
             vals[3 * i + 2] = Acc(0);
         }
-        if (threadIdx.x == 0) *used = 0u;
     }
 
     __device__ __forceinline__ void add(uint32_t leaf, T w, const T F[3])
     {
         const uint32_t key = leaf + 1u;
-        const uint32_t step = ((leaf * 0x9E3779B1u) >> 16) | 1u;
         const Acc a0 = to_acc<T, MODE>(w, F[0], scale);
         const Acc a1 = to_acc<T, MODE>(w, F[1], scale);
         const Acc a2 = to_acc<T, MODE>(w, F[2], scale);
-        // find (or claim) the slot; the adds follow once the lanes reconverge
+        // primary slot first; further probes only for the lanes that collided
         uint32_t slot = leaf & (S - 1);
-        bool found = false;
+        uint32_t cur = keys[slot];
+        if (cur == 0u) {
+            cur = atomicCAS(&keys[slot], 0u, key);
+            if (cur == 0u) cur = key;
+        }
+        bool found = cur == key;
+        if (!found) {
+            const uint32_t step = ((leaf * 0x9E3779B1u) >> 16) | 1u;
 #pragma unroll 1
-        for (int p = 0; p < kProbe; ++p) {
-            uint32_t cur = keys[slot];
-            if (cur == 0u) {
-                cur = atomicCAS(&keys[slot], 0u, key);
+            for (int p = 1; p < kProbe; ++p) {
+                slot = (slot + step) & (S - 1);
+                cur = keys[slot];
                 if (cur == 0u) {
-                    cur = key;
-                    atomicAdd(used, 1u);
+                    cur = atomicCAS(&keys[slot], 0u, key);
+                    if (cur == 0u) cur = key;
+                }
+                if (cur == key) {
+                    found = true;
+                    break;
                 }
             }
-            if (cur == key) {
-                found = true;
-                break;
-            }
-            slot = (slot + step) & (S - 1);
         }
         if (found) {
             atomicAdd(&vals[3 * slot], a0);
@@ -229,24 +231,10 @@ struct LdsSink {
             }
         }
         __syncthreads();
-        if (threadIdx.x == 0) *used = 0u;
-        __syncthreads();
-    }
-
-    // Flush when the table is getting full (all threads of the workgroup).
-    __device__ __forceinline__ void maybe_flush()
-    {
-        __syncthreads();
-        const uint32_t u = *used;
-        if (u > (uint32_t)(S / 2)) flush();
     }
 };
 
-// One point.  The 27 node lookups are issued together, then the 27 field
-// gathers, then the spreading, so each phase's loads overlap.  k indexes the
-// point's data through perm when given (sorted processing); ids are written
-// at the data index.
-template <typename T, int OPS, typename Sink>
+template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const int32_t *__restrict__ perm,
                                             const T *__restrict__ pos, const T *__restrict__ field,
                                             const T *__restrict__ force, int32_t *__restrict__ ids,
@@ -263,7 +251,7 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
     T U[3] = {T(0), T(0), T(0)};
     if (ok) {
         Stencil<T> st;
-        make_stencil<T>(tv, X, I, e, st);
+        make_stencil<T, PER>(tv, X, I, e, st);
         // phase 1: root-table entries of the 27 nodes (independent loads);
         // nodes dropped at a non-periodic wall are not looked up
         uint32_t ent[27];
@@ -272,15 +260,20 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
             const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
             const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
             if (q == 13) ent[q] = st.host | ((uint32_t)st.level << kLevelShift);
-            else if ((st.valid & need) != need) ent[q] = 0u;
+            else if (!PER && (st.valid & need) != need) ent[q] = 0u;
             else ent[q] = __ldg(tv.table + (st.R[0][ox] | (st.R[1][oy] << 1) | (st.R[2][oz] << 2)));
         }
         // phase 2: nodes inside split root cells continue the descent (rare)
+        uint32_t any = 0u;
 #pragma unroll
-        for (int q = 0; q < 27; ++q) {
-            if (ent[q] & kSplit) {
-                const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
-                ent[q] = descend_below_root(tv, ent[q], st.N[0][ox], st.N[1][oy], st.N[2][oz]);
+        for (int q = 0; q < 27; ++q) any |= ent[q];
+        if (any & kSplit) {
+#pragma unroll
+            for (int q = 0; q < 27; ++q) {
+                if (ent[q] & kSplit) {
+                    const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+                    ent[q] = descend_below_root(tv, ent[q], st.N[0][ox], st.N[1][oy], st.N[2][oz]);
+                }
             }
         }
         // phase 3: interpolation gathers
@@ -289,12 +282,12 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
             for (int q = 0; q < 27; ++q) {
                 const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
                 const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
-                if ((st.valid & need) != need) continue;
+                if (!PER && (st.valid & need) != need) continue;
                 const int64_t j = 3 * (int64_t)(ent[q] & kIdMask);
                 const T w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
-                U[0] += w * field[j];
-                U[1] += w * field[j + 1];
-                U[2] += w * field[j + 2];
+                U[0] = fma(w, field[j], U[0]);
+                U[1] = fma(w, field[j + 1], U[1]);
+                U[2] = fma(w, field[j + 2], U[2]);
             }
         }
         // phase 4: spreading
@@ -304,7 +297,7 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
             for (int q = 0; q < 27; ++q) {
                 const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
                 const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
-                if ((st.valid & need) != need) continue;
+                if (!PER && (st.valid & need) != need) continue;
                 sink.add(ent[q] & kIdMask, st.w[0][ox] * st.w[1][oy] * st.w[2][oz], F);
             }
         }
@@ -329,7 +322,8 @@ __device__ __forceinline__ void grad_point(const TreeView &tv, int64_t k, const 
     if (ok) {
         const uint32_t e = descend(tv, I[0], I[1], I[2]);
         Stencil<T> st;
-        make_stencil<T>(tv, X, I, e, st);
+        if (tv.periodic) make_stencil<T, true>(tv, X, I, e, st);
+        else make_stencil<T, false>(tv, X, I, e, st);
         T dw[3][3];
         const T sc = (T)(1 << st.level);
 #pragma unroll
@@ -351,10 +345,11 @@ __device__ __forceinline__ void grad_point(const TreeView &tv, int64_t k, const 
                     if ((st.valid & need) != need) continue;
                     const uint32_t leaf = (ox == 1 && oy == 1 && oz == 1) ? st.host : node_leaf<T>(tv, st, ox, oy, oz);
                     const int64_t j = 3 * (int64_t)leaf;
-                    const T dot = v0 * field[j] + v1 * field[j + 1] + v2 * field[j + 2];
-                    G[0] += dot * dw[0][ox] * st.w[1][oy] * st.w[2][oz];
-                    G[1] += dot * st.w[0][ox] * dw[1][oy] * st.w[2][oz];
-                    G[2] += dot * st.w[0][ox] * st.w[1][oy] * dw[2][oz];
+                    const T dot = fma(v0, field[j], fma(v1, field[j + 1], v2 * field[j + 2]));
+                    const T wyz = st.w[1][oy] * st.w[2][oz];
+                    G[0] = fma(dot * dw[0][ox], wyz, G[0]);
+                    G[1] = fma(dot * st.w[0][ox], dw[1][oy] * st.w[2][oz], G[1]);
+                    G[2] = fma(dot * st.w[0][ox], st.w[1][oy] * dw[2][oz], G[2]);
                 }
             }
         }
@@ -440,14 +435,14 @@ __global__ void k_fx_finalize(const unsigned long long *__restrict__ acc, T *__r
 }
 
 // Process points [start, end) of one tile with all threads of the workgroup.
-template <typename T, int OPS, typename Sink>
+template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, int64_t end,
                                             const int32_t *__restrict__ perm, const T *__restrict__ pos,
                                             const T *__restrict__ field, const T *__restrict__ force,
                                             int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink)
 {
     for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x)
-        track_point<T, OPS, Sink>(tv, k, perm, pos, field, force, ids, vel, sink);
+        track_point<T, OPS, PER, Sink>(tv, k, perm, pos, field, force, ids, vel, sink);
 }
 
 // LDS table size of the aggregating sink, per precision and mode
