@@ -69,8 +69,9 @@ extern "C" {
 /* Spreading accumulation.  ATOMIC: atomic adds in the working precision
  * (FP32 or FP64), order dependent in the last bits.  FIXED: every
  * contribution is rounded once to a signed 64-bit fixed-point value
- * q = rint(w F 2^s) (w F formed exactly in FP64 for FP32 inputs, in FP64
- * arithmetic for FP64 inputs; ties to even) and summed with integer adds, so
+ * q = rint(w F 2^s), ties to even, formed with one FP64 fused multiply-add
+ * (exact product for FP32 inputs, the exact FP64 product rounded once for
+ * FP64 inputs) and summed with integer adds, so
  * the result does not depend on execution order (bitwise reproducible).
  * s = min(62 - E, 51 - Ef) with 2^E >= n max|F| and 2^Ef >= max|F| (no leaf
  * sum can overflow, no contribution exceeds 2^51); max over finite
@@ -108,12 +109,12 @@ typedef struct {
     int32_t flags;        /* OT_TUNE_* bits                                           */
 } ot_tuning;
 
-/* Sort the points by host leaf inside every run before the persistent pass
- * (locate, LDS radix sort of the top 16 bits of the host ids into
- * plan-owned buffers; the pass then visits the points in that order through
- * the permutation).  Neighbouring threads then share stencil nodes in cache
- * and in the workgroup's spreading table.  Results are written at each
- * point's own row as before.  Needs the same ops for every instance. */
+/* Sort the points by host leaf before the persistent pass: locate, then
+ * two stable radix passes over the top 16 bits of the host ids that carry
+ * positions and forces into plan-owned buffers; the pass then visits the
+ * points in that order and writes each result at its point's input row.
+ * Neighbouring threads then share stencil nodes in cache and in the
+ * workgroup's spreading table.  Needs the same ops for every instance. */
 #define OT_TUNE_SORT_POINTS 1
 
 /* Morton keys of leaf anchors (Sec. 3.1: leaves are ordered along the

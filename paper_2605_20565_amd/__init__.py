@@ -16,7 +16,8 @@ from typing import Optional, Sequence, Tuple
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libocttrack.so")
+# OCTRACK_LIB: load another build of the library (e.g. a profiling build)
+LIB_PATH = os.environ.get("OCTRACK_LIB") or os.path.join(_HERE, "libocttrack.so")
 
 OT_OK = 0
 OT_F32, OT_F64 = 0, 1

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ot_common.h"
+#include "point_sort.h"
 #include "track_device.h"
 
 namespace ot {
@@ -41,16 +42,18 @@ struct ot_batch_plan {
     bool sort_points;
     int sort_bits, sort_shift;
     int ops_all;              // the common ops of every instance
-    uint64_t *skey[2];
+    uint32_t *skey[2];
     int32_t *sval[2];
-    void *sws;                // radix sort workspace
+    void *spos[2], *sforce[2];   // positions / forces in sorted order
+    void *sws;                // counting workspace
 };
 
 namespace ot {
 namespace {
 
 constexpr uint32_t kCountMask = 0x00FFFFFFu;
-constexpr int kSortKeyBits = 16;   // two radix passes
+constexpr int kSortKeyBits = 16;   // two 8-bit passes
+
 
 template <typename T, int MODE, bool PER>
 __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__restrict__ tile_start,
@@ -64,7 +67,7 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
     constexpr int S = SinkSlots<T, MODE>::value;
     using Acc = typename AccType<T, MODE>::type;
     __shared__ uint32_t keys[S];
-    __shared__ Acc vals[3 * S];
+    __shared__ Acc vals[LdsSink<T, MODE, S>::kVals];
     __shared__ unsigned s_tile;
     const double scale = MODE == kModeFixed ? fx->scale : 0.0;
     LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
@@ -89,24 +92,6 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
     }
 }
 
-// Sort keys: host leaf id >> shift (n_leaves for points without a host, so
-// they sort last): points end up grouped in runs of 2^shift consecutive
-// leaves, enough for cache and table locality.  Values: the point's index.
-// Writes ids when asked.
-template <typename T>
-__global__ void k_sort_keys(TreeView tv, int64_t n, const T *__restrict__ pos, int32_t *__restrict__ ids,
-                            uint64_t *__restrict__ keys, int32_t *__restrict__ vals, uint32_t none, int shift)
-{
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    uint32_t I[3];
-    const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
-    const uint32_t host = ok ? (descend(tv, I[0], I[1], I[2]) & kIdMask) : none;
-    if (ids) ids[k] = ok ? (int32_t)host : -1;
-    keys[k] = host >> shift;
-    vals[k] = (int32_t)k;
-}
-
 template <typename T, int MODE>
 int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids, void *vel,
             void *fout, hipStream_t s)
@@ -119,26 +104,30 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
         if ((rc = spread_prologue(t, p->dtype, p->mode, 0, force, n, fout, s))) return rc;
     const int32_t *perm = nullptr;
     int32_t *kids = ids;
+    const T *kpos = (const T *)pos, *kforce = (const T *)force;
     if (p->sort_points && n > 0) {
-        const unsigned gb = (unsigned)((n + 255) / 256);
-        hipLaunchKernelGGL(k_sort_keys<T>, dim3(gb), dim3(256), 0, s, t->view, n, (const T *)pos,
-                           (p->ops_all & kOpLocate) ? ids : (int32_t *)nullptr, p->skey[0], p->sval[0],
-                           (uint32_t)t->n_leaves, p->sort_shift);
-        uint64_t *kr;
-        int32_t *vr;
-        radix_sort_pairs(p->skey[0], p->sval[0], p->skey[1], p->sval[1], n, p->sort_bits, p->sws, &kr, &vr, s);
-        perm = vr;
+        // ids come from the key pass; positions and forces travel with the keys
+        const bool carry_force = (p->ops_all & kOpSpread) != 0;
+        PointSortBufs<T> b{{p->skey[0], p->skey[1]},
+                           {p->sval[0], p->sval[1]},
+                           {(T *)p->spos[0], (T *)p->spos[1]},
+                           {(T *)p->sforce[0], (T *)p->sforce[1]},
+                           p->sws};
+        PointSortResult<T> r;
+        point_sort<T>(t->view, n, t->n_leaves, p->sort_shift, p->sort_bits, (const T *)pos,
+                      carry_force ? (const T *)force : nullptr, (p->ops_all & kOpLocate) ? ids : nullptr, b, s, r);
+        perm = r.perm;
+        kpos = r.pos;
+        kforce = carry_force ? r.force : nullptr;
         kids = nullptr;
     }
     if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
     if (t->view.periodic)
         hipLaunchKernelGGL((k_batch<T, MODE, true>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start,
-                           p->tile_info, p->n_tiles, p->counter, perm, (const T *)pos, (const T *)field,
-                           (const T *)force, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+                           p->tile_info, p->n_tiles, p->counter, perm, kpos, (const T *)field, kforce, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
     else
         hipLaunchKernelGGL((k_batch<T, MODE, false>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start,
-                           p->tile_info, p->n_tiles, p->counter, perm, (const T *)pos, (const T *)field,
-                           (const T *)force, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+                           p->tile_info, p->n_tiles, p->counter, perm, kpos, (const T *)field, kforce, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
     OT_HIP(hipGetLastError());
     if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
     if (p->ops_union & kOpSpread)
@@ -179,12 +168,12 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     if (!tree || !offsets || !ops || n_inst <= 0) return fail(OT_ERR_INVALID, "ot_batch_plan_create: bad arguments");
     if (dtype != OT_F32 && dtype != OT_F64) return fail(OT_ERR_INVALID, "dtype must be OT_F32 or OT_F64");
     if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
+    const bool sort_points = tuning && (tuning->flags & OT_TUNE_SORT_POINTS);
     int block = tuning && tuning->block ? tuning->block : 512;
     int tile = tuning && tuning->tile ? tuning->tile : 4 * block;
     if (block < 64 || block > 512 || block % 64) return fail(OT_ERR_INVALID, "block must be a multiple of 64 in [64, 512]");
     if (tile < block || tile % block || tile > (int)kCountMask) return fail(OT_ERR_INVALID, "tile must be a multiple of block");
     if (offsets[0] != 0) return fail(OT_ERR_INVALID, "offsets[0] must be 0");
-    const bool sort_points = tuning && (tuning->flags & OT_TUNE_SORT_POINTS);
     if (sort_points && offsets[n_inst] > (int64_t)INT32_MAX)
         return fail(OT_ERR_CAPACITY, "point sorting indexes points with int32: at most 2^31 - 1 points");
     std::vector<int64_t> starts;
@@ -234,12 +223,15 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
         while ((int64_t(1) << bits) <= tree->n_leaves) ++bits;   // keys go up to n_leaves
         p->sort_shift = std::max(0, bits - kSortKeyBits);
         p->sort_bits = bits - p->sort_shift;
+        const size_t vec = 3 * (size_t)n * (dtype == OT_F32 ? 4 : 8);
         hipError_t e = hipSuccess;
-        if (e == hipSuccess) e = hipMalloc((void **)&p->skey[0], 8 * (size_t)n);
-        if (e == hipSuccess) e = hipMalloc((void **)&p->skey[1], 8 * (size_t)n);
-        if (e == hipSuccess) e = hipMalloc((void **)&p->sval[0], 4 * (size_t)n);
-        if (e == hipSuccess) e = hipMalloc((void **)&p->sval[1], 4 * (size_t)n);
-        if (e == hipSuccess) e = hipMalloc(&p->sws, (size_t)radix_ws_bytes(n));
+        for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+            e = hipMalloc((void **)&p->skey[i], 4 * (size_t)n);
+            if (e == hipSuccess) e = hipMalloc((void **)&p->sval[i], 4 * (size_t)n);
+            if (e == hipSuccess) e = hipMalloc(&p->spos[i], vec);
+            if (e == hipSuccess && (ops_all & kOpSpread)) e = hipMalloc(&p->sforce[i], vec);
+        }
+        if (e == hipSuccess) e = hipMalloc(&p->sws, (size_t)point_sort_ws_bytes(n));
 
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -364,7 +356,8 @@ extern "C" int ot_batch_plan_destroy(ot_batch_plan *p)
     drop_graph(p);
     if (p->ev[0]) (void)hipEventDestroy(p->ev[0]);
     if (p->ev[1]) (void)hipEventDestroy(p->ev[1]);
-    for (void *q : {(void *)p->skey[0], (void *)p->skey[1], (void *)p->sval[0], (void *)p->sval[1], p->sws})
+    for (void *q : {(void *)p->skey[0], (void *)p->skey[1], (void *)p->sval[0], (void *)p->sval[1], p->spos[0],
+                    p->spos[1], p->sforce[0], p->sforce[1], p->sws})
         if (q) (void)hipFree(q);
     if (p->tile_start) (void)hipFree(p->tile_start);
     if (p->tile_info) (void)hipFree(p->tile_info);

@@ -121,6 +121,20 @@ __device__ __forceinline__ void delta3(T t, T w[3])
     w[2] = T(2) * t * t / (T(2) + T(3) * u + q);
 }
 
+// FP32: the hardware square root and reciprocal (about 1 ulp each) instead
+// of the correctly rounded sequences; 1 - 3u^2 lies in [1/4, 1] and the two
+// denominators in [1, 9/2], so neither meets a special case.
+template <>
+__device__ __forceinline__ void delta3<float>(float t, float w[3])
+{
+    const float u = t - 0.5f;
+    const float q = __builtin_amdgcn_sqrtf(1.0f - 3.0f * u * u);
+    const float s = 1.0f - t;
+    w[0] = 2.0f * s * s * __builtin_amdgcn_rcpf(2.0f - 3.0f * u + q);
+    w[1] = (1.0f + q) * (1.0f / 3.0f);
+    w[2] = 2.0f * t * t * __builtin_amdgcn_rcpf(2.0f + 3.0f * u + q);
+}
+
 template <typename T>
 __device__ __forceinline__ void delta3_grad(T t, T w[3], T dw[3])
 {

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
         constexpr int S = SinkSlots<T, MODE>::value;
         using Acc = typename AccType<T, MODE>::type;
         __shared__ uint32_t keys[S];
-        __shared__ Acc vals[3 * S];
+        __shared__ Acc vals[LdsSink<T, MODE, S>::kVals];
         const double scale = MODE == kModeFixed ? fx->scale : 0.0;
         LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
         sink.clear();

@@ -101,21 +101,23 @@ struct AccType { using type = T; };
 template <typename T>
 struct AccType<T, kModeFixed> { using type = unsigned long long; };
 
-// Fixed point: q = rint(w F 2^s) with w F formed exactly in FP64 for FP32
-// inputs (a 24 x 24-bit product fits 53 bits) and in FP64 arithmetic for
-// FP64 inputs; |w F 2^s| <= 2^51 by the choice of s, so adding 1.5 * 2^52
-// rounds to the nearest integer (ties to even) and leaves it, in two's
-// complement, in the low mantissa bits.
-__device__ __forceinline__ unsigned long long fx_round(double x)
+// Fixed point: q = rint(w F 2^s), formed by one FP64 fused multiply-add
+// fma(w, F 2^s, 1.5 * 2^52): the product is rounded once, together with the
+// addition, and since |w F 2^s| <= 2^51 by the choice of s the sum lies in
+// [2^52, 2^53), where the spacing is 1, so the rounding is to the nearest
+// integer (ties to even), held in two's complement in the low mantissa bits.
+// For FP32 inputs the product is exact, so q is exactly rint of the exact
+// value w F 2^s.  fs = (double)F * 2^s is exact and formed once per point.
+__device__ __forceinline__ unsigned long long fx_round_fma(double w, double fs)
 {
     const double magic = 6755399441055744.0;   // 1.5 * 2^52
-    return (unsigned long long)(__double_as_longlong(x + magic) - __double_as_longlong(magic));
+    return (unsigned long long)(__double_as_longlong(fma(w, fs, magic)) - __double_as_longlong(magic));
 }
 
 template <typename T, int MODE>
 __device__ __forceinline__ typename AccType<T, MODE>::type to_acc(T w, T f, double scale)
 {
-    if constexpr (MODE == kModeFixed) return fx_round((double)w * ((double)f * scale));
+    if constexpr (MODE == kModeFixed) return fx_round_fma((double)w, (double)f * scale);
     else return w * f;
 }
 
@@ -139,6 +141,14 @@ struct DirectSink {
 #pragma unroll
         for (int c = 0; c < 3; ++c) global_add<T, MODE>(fout, facc, j + c, to_acc<T, MODE>(w, F[c], scale));
     }
+
+    // All 27 stencil nodes of one point; bit q of live: node q exists.
+    __device__ __forceinline__ void add27(const uint32_t (&ent)[27], uint32_t live, const T (&w)[3][3], const T F[3])
+    {
+#pragma unroll
+        for (int q = 0; q < 27; ++q)
+            if ((live >> q) & 1u) add(ent[q] & kIdMask, w[0][q % 3] * w[1][(q / 3) % 3] * w[2][q / 9], F);
+    }
 };
 
 // Workgroup-local aggregation: an open-addressing table in LDS keyed by leaf
@@ -155,8 +165,9 @@ template <typename T, int MODE, int S>
 struct LdsSink {
     using Acc = typename AccType<T, MODE>::type;
     static constexpr int kProbe = 8;
+    static constexpr int kVals = 3 * S;
     uint32_t *keys;     // S, 0 = empty, else leaf + 1
-    Acc *vals;          // 3 S
+    Acc *vals;          // kVals
     T *fout;
     unsigned long long *facc;
     double scale;
@@ -171,34 +182,25 @@ struct LdsSink {
         }
     }
 
-    __device__ __forceinline__ void add(uint32_t leaf, T w, const T F[3])
+    // Slots after the primary one (double hashing); device memory when none
+    // is free within kProbe steps.
+    __device__ __forceinline__ void add_probing(uint32_t leaf, Acc a0, Acc a1, Acc a2)
     {
         const uint32_t key = leaf + 1u;
-        const Acc a0 = to_acc<T, MODE>(w, F[0], scale);
-        const Acc a1 = to_acc<T, MODE>(w, F[1], scale);
-        const Acc a2 = to_acc<T, MODE>(w, F[2], scale);
-        // primary slot first; further probes only for the lanes that collided
+        const uint32_t step = ((leaf * 0x9E3779B1u) >> 16) | 1u;
         uint32_t slot = leaf & (S - 1);
-        uint32_t cur = keys[slot];
-        if (cur == 0u) {
-            cur = atomicCAS(&keys[slot], 0u, key);
-            if (cur == 0u) cur = key;
-        }
-        bool found = cur == key;
-        if (!found) {
-            const uint32_t step = ((leaf * 0x9E3779B1u) >> 16) | 1u;
+        bool found = false;
 #pragma unroll 1
-            for (int p = 1; p < kProbe; ++p) {
-                slot = (slot + step) & (S - 1);
-                cur = keys[slot];
-                if (cur == 0u) {
-                    cur = atomicCAS(&keys[slot], 0u, key);
-                    if (cur == 0u) cur = key;
-                }
-                if (cur == key) {
-                    found = true;
-                    break;
-                }
+        for (int p = 1; p < kProbe; ++p) {
+            slot = (slot + step) & (S - 1);
+            uint32_t cur = keys[slot];
+            if (cur == 0u) {
+                cur = atomicCAS(&keys[slot], 0u, key);
+                if (cur == 0u) cur = key;
+            }
+            if (cur == key) {
+                found = true;
+                break;
             }
         }
         if (found) {
@@ -210,6 +212,43 @@ struct LdsSink {
             global_add<T, MODE>(fout, facc, j, a0);
             global_add<T, MODE>(fout, facc, j + 1, a1);
             global_add<T, MODE>(fout, facc, j + 2, a2);
+        }
+    }
+
+    // All 27 stencil nodes of one point; bit q of live: node q exists.  Every
+    // node first claims or finds its primary slot with one compare-and-swap
+    // (0 -> key; a slot holding the key is left as it is); the 27 swaps are
+    // independent, so they are in flight together instead of a chain of LDS
+    // round trips per node.  Keys are only removed by flush(), after a
+    // barrier, so a slot that reads as this key stays this key's.  A node
+    // whose primary slot holds another key probes further.
+    __device__ __forceinline__ void add27(const uint32_t (&ent)[27], uint32_t live, const T (&w)[3][3], const T F[3])
+    {
+        uint32_t hit = 0u;
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            if ((live >> q) & 1u) {
+                const uint32_t leaf = ent[q] & kIdMask;
+                const uint32_t old = atomicCAS(&keys[leaf & (S - 1)], 0u, leaf + 1u);
+                hit |= (uint32_t)(old == 0u || old == leaf + 1u) << q;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 27; ++q) {
+            if (!((live >> q) & 1u)) continue;
+            const uint32_t leaf = ent[q] & kIdMask;
+            const T wq = w[0][q % 3] * w[1][(q / 3) % 3] * w[2][q / 9];
+            const Acc a0 = to_acc<T, MODE>(wq, F[0], scale);
+            const Acc a1 = to_acc<T, MODE>(wq, F[1], scale);
+            const Acc a2 = to_acc<T, MODE>(wq, F[2], scale);
+            if ((hit >> q) & 1u) {
+                const uint32_t slot = leaf & (S - 1);
+                atomicAdd(&vals[3 * slot], a0);
+                atomicAdd(&vals[3 * slot + 1], a1);
+                atomicAdd(&vals[3 * slot + 2], a2);
+            } else {
+                add_probing(leaf, a0, a1, a2);
+            }
         }
     }
 
@@ -240,8 +279,10 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
                                             const T *__restrict__ force, int32_t *__restrict__ ids,
                                             T *__restrict__ vel, Sink &sink)
 {
+    // With a permutation, positions and forces are already in sorted order
+    // (index k) and the per-point outputs go to the input index perm[k].
     const int64_t kd = perm ? (int64_t)perm[k] : k;
-    const T X[3] = {pos[3 * kd], pos[3 * kd + 1], pos[3 * kd + 2]};
+    const T X[3] = {pos[3 * k], pos[3 * k + 1], pos[3 * k + 2]};
     uint32_t I[3];
     const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
     const uint32_t e = ok ? descend(tv, I[0], I[1], I[2]) : 0u;
@@ -292,14 +333,21 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
         }
         // phase 4: spreading
         if (OPS & kOpSpread) {
-            const T F[3] = {force[3 * kd], force[3 * kd + 1], force[3 * kd + 2]};
+            // finish the gathers first: without the barrier the compiler may
+            // sink the interpolation sums below the spreading and keep all
+            // 27 gathered values alive through it
+            if (OPS & kOpInterp) asm volatile("" : "+v"(U[0]), "+v"(U[1]), "+v"(U[2]));
+            const T F[3] = {force[3 * k], force[3 * k + 1], force[3 * k + 2]};
+            uint32_t live = (1u << 27) - 1u;
+            if (!PER) {
 #pragma unroll
-            for (int q = 0; q < 27; ++q) {
-                const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
-                const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
-                if (!PER && (st.valid & need) != need) continue;
-                sink.add(ent[q] & kIdMask, st.w[0][ox] * st.w[1][oy] * st.w[2][oz], F);
+                for (int q = 0; q < 27; ++q) {
+                    const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+                    const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
+                    if ((st.valid & need) != need) live &= ~(1u << q);
+                }
             }
+            sink.add27(ent, live, st.w, F);
         }
     }
     if (OPS & kOpInterp) {

@@ -37,9 +37,9 @@ def default_candidates(n_points: int, uniform_ops: bool = True) -> List[Candidat
     out = []
     for sort in sorts:
         for block in (256, 512):
-            for mult in (2, 4, 8):
+            for mult in (1, 2, 4, 8):
                 tile = block * mult
-                if tile > max(block, n_points):
+                if tile > max(block, n_points) or (sort and mult == 8) or (not sort and mult == 1):
                     continue
                 out.append(Candidate(block, tile, 0, sort))
     return out
