@@ -117,7 +117,7 @@ def main():
     ap.add_argument("--presorted", action="store_true",
                     help="store the points in host-leaf order before timing (the layout a simulation that keeps "
                          "its particles sorted maintains) and run without the in-step sort")
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="points in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=3_000_000, help="points in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip side measurements")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -323,6 +323,24 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
         pl.close()
     res["spread_mode_ms_per_step"] = modes
 
+    # FIXED mode is bitwise reproducible: five runs of the batched plan
+    outs = []
+    for _ in range(5):
+        ids = torch.empty(n, dtype=torch.int32, device=dev)
+        vel = torch.empty((n, 3), dtype=dt, device=dev)
+        fo = torch.empty((tree.n_leaves, 3), dtype=dt, device=dev)
+        plan.run(pos, field=field, force=force, ids=ids, vel=vel, field_out=fo)
+        torch.cuda.synchronize()
+        outs.append((ids.clone(), vel.clone(), fo.clone()))
+    res["fixed_bitwise_repro_5_runs"] = args.mode == "fixed" and all(
+        all(torch.equal(a.view(torch.uint8) if a.is_floating_point() else a,
+                        b.view(torch.uint8) if b.is_floating_point() else b) for a, b in zip(outs[0], o))
+        for o in outs[1:])
+    del outs
+
+    # launch latency on the small workload 1 (11k points; latency bound, so no roofline figure)
+    res["config1_latency_us"] = config1_latency(dev, dt, args.mode, ot, torch, timeit)
+
     # copy bandwidth for context
     a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
@@ -333,6 +351,27 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
     # error against the oracle on a sample of the same inputs
     res["error_vs_oracle"] = oracle_check(w, tree, dev, dt, torch)
     return res
+
+
+def config1_latency(dev, dt, mode, ot, torch, timeit):
+    import synth
+    w1 = synth.workload(1)
+    t1 = ot.Tree.from_anchors(torch.from_numpy(w1.tree.anchors.astype(np.int32)).to(dev),
+                              torch.from_numpy(w1.tree.levels).to(dev), w1.tree.l_min, w1.tree.l_max, w1.tree.periodic)
+    P = torch.from_numpy(w1.points).to(dev, dt)
+    F = torch.from_numpy(w1.forces).to(dev, dt)
+    U = t1.permute_rows(torch.from_numpy(w1.field).to(dev, dt))
+    n = P.shape[0]
+    ids = torch.empty(n, dtype=torch.int32, device=dev)
+    vel = torch.empty((n, 3), dtype=dt, device=dev)
+    fo = torch.empty((t1.n_leaves, 3), dtype=dt, device=dev)
+    plain = timeit(lambda: t1.track(P, field=U, force=F, mode=mode, ids=ids, vel=vel, field_out=fo), 50)
+    offs = [int(v) for v in w1.instances]
+    pl = ot.BatchPlan(t1, offs, [7] * (len(offs) - 1), dtype=dt, mode=mode)
+    batched = timeit(lambda: pl.run(P, field=U, force=F, ids=ids, vel=vel, field_out=fo), 50)
+    pl.close()
+    return {"points": n, "leaves": t1.n_leaves, "plain_fused_launch": round(plain * 1e3, 1),
+            "batched_graph": round(batched * 1e3, 1)}
 
 
 def oracle_check(w, tree, dev, dt, torch, n_sample=20000):
@@ -381,10 +420,28 @@ def cpu_baseline(w, n_sample):
     o.interpolate(fld, pts)
     o.spread(frc, pts)
     el = time.perf_counter() - t
-    log(f"[bench] oracle: {m} points in {el:.1f}s on {oracle.num_threads()} threads")
-    return {"value": m / el, "unit": "points/s", "cores": oracle.num_threads(), "kind": "oracle",
+    threads = oracle.num_threads()
+    log(f"[bench] oracle: {m} points in {el:.1f}s on {threads} threads")
+    # the same on one thread, on a tenth of the sample
+    m1 = max(1, m // 10)
+    oracle.set_num_threads(1)
+    t = time.perf_counter()
+    o.locate(pts[:m1])
+    o.interpolate(fld, pts[:m1])
+    o.spread(frc[:m1], pts[:m1])
+    el1 = time.perf_counter() - t
+    oracle.set_num_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": m / el, "unit": "points/s", "cores": threads, "kind": "oracle",
             "sample": f"{m} points drawn uniformly from the {w.n_points}-point workload, full tree; "
-                      f"locate+interpolate+spread in FP64, {el:.1f}s"}
+                      f"locate+interpolate+spread in FP64, {el:.1f}s",
+            "single_thread_value": m1 / el1, "single_thread_sample": f"first {m1} points of the sample, {el1:.1f}s",
+            "cpu_model": model, "nproc": os.cpu_count()}
 
 
 if __name__ == "__main__":

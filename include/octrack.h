@@ -101,7 +101,9 @@ typedef struct {
     int64_t workspace_bytes; /* device bytes of the fixed-point spreading workspace   */
 } ot_tree_info;
 
-/* Tuning of the batched persistent pass. Zero fields take defaults. */
+/* Tuning of the batched persistent pass.  Zero fields take defaults: 512
+ * threads and 4 points per thread, narrowed (down to 64 threads, 1 point
+ * per thread) when the run has too few points for two workgroups per CU. */
 typedef struct {
     int32_t block;        /* threads per workgroup (multiple of 64, <= 512)           */
     int32_t tile;         /* points per tile (multiple of block)                      */

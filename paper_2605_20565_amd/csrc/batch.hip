@@ -17,8 +17,8 @@
 #include "track_device.h"
 
 namespace ot {
-int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const void *force, int64_t n, void *fout,
-                    hipStream_t s);
+int spread_begin(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
+int spread_scale(const ot_tree *t, int dtype, int mode, const void *force, int64_t n, hipStream_t s);
 int spread_epilogue(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
 }  // namespace ot
 
@@ -42,9 +42,8 @@ struct ot_batch_plan {
     bool sort_points;
     int sort_bits, sort_shift;
     int ops_all;              // the common ops of every instance
-    uint32_t *skey[2];
-    int32_t *sval[2];
-    void *spos[2], *sforce[2];   // positions / forces in sorted order
+    uint64_t *skv[2];         // host << 32 | input index, in sorted order
+    void *srec[2];            // position (+ force) records in sorted order
     void *sws;                // counting workspace
 };
 
@@ -58,8 +57,8 @@ constexpr int kSortKeyBits = 16;   // two 8-bit passes
 template <typename T, int MODE, bool PER>
 __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__restrict__ tile_start,
                                                const uint32_t *__restrict__ tile_info, int64_t n_tiles,
-                                               unsigned *__restrict__ counter, const int32_t *__restrict__ perm,
-                                               const T *__restrict__ pos,
+                                               unsigned *__restrict__ counter, const uint64_t *__restrict__ kv,
+                                               int rs, const T *__restrict__ pos,
                                                const T *__restrict__ field, const T *__restrict__ force,
                                                int32_t *__restrict__ ids, T *__restrict__ vel, T *__restrict__ fout,
                                                unsigned long long *__restrict__ facc, const FxState *__restrict__ fx)
@@ -83,7 +82,7 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
         const int64_t end = start + (int64_t)(info & kCountMask);
         switch (info >> 24) {
 #define OT_CASE(OPSV) \
-    case OPSV: track_range<T, OPSV, PER>(tv, start, end, perm, pos, field, force, ids, vel, sink); break;
+    case OPSV: track_range<T, OPSV, PER>(tv, start, end, kv, rs, pos, field, force, ids, vel, sink); break;
             OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
 #undef OT_CASE
         default: break;
@@ -100,34 +99,39 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
     const int64_t n = p->n_points;
     hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, p->counter, (int64_t)1, 0u);
     int rc;
-    if (p->ops_union & kOpSpread)
-        if ((rc = spread_prologue(t, p->dtype, p->mode, 0, force, n, fout, s))) return rc;
-    const int32_t *perm = nullptr;
+    const bool spread = (p->ops_union & kOpSpread) != 0;
+    if (spread && (rc = spread_begin(t, p->dtype, p->mode, 0, fout, s))) return rc;
+    const uint64_t *kv = nullptr;
+    int rs = 3;
     int32_t *kids = ids;
     const T *kpos = (const T *)pos, *kforce = (const T *)force;
+    const void *scale_from = force;   // max |F| still to take (FIXED)
     if (p->sort_points && n > 0) {
-        // ids come from the key pass; positions and forces travel with the keys
+        // ids come from the key pass; positions and forces travel with the
+        // keys, and the first pass takes max |F| on the way
         const bool carry_force = (p->ops_all & kOpSpread) != 0;
-        PointSortBufs<T> b{{p->skey[0], p->skey[1]},
-                           {p->sval[0], p->sval[1]},
-                           {(T *)p->spos[0], (T *)p->spos[1]},
-                           {(T *)p->sforce[0], (T *)p->sforce[1]},
-                           p->sws};
+        PointSortBufs<T> b{{p->skv[0], p->skv[1]}, {(T *)p->srec[0], (T *)p->srec[1]}, p->sws};
         PointSortResult<T> r;
+        unsigned long long *maxbits =
+            (carry_force && p->mode == OT_SPREAD_FIXED) ? &((FxState *)t->scratch)->maxbits : nullptr;
         point_sort<T>(t->view, n, t->n_leaves, p->sort_shift, p->sort_bits, (const T *)pos,
-                      carry_force ? (const T *)force : nullptr, (p->ops_all & kOpLocate) ? ids : nullptr, b, s, r);
-        perm = r.perm;
-        kpos = r.pos;
-        kforce = carry_force ? r.force : nullptr;
+                      carry_force ? (const T *)force : nullptr, (p->ops_all & kOpLocate) ? ids : nullptr, b, maxbits,
+                      s, r);
+        kv = r.kv;
+        rs = r.stride;
+        kpos = r.rec;
+        kforce = carry_force ? r.rec + 3 : nullptr;
         kids = nullptr;
+        if (maxbits) scale_from = nullptr;
     }
+    if (spread && (rc = spread_scale(t, p->dtype, p->mode, scale_from, n, s))) return rc;
     if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
     if (t->view.periodic)
         hipLaunchKernelGGL((k_batch<T, MODE, true>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start,
-                           p->tile_info, p->n_tiles, p->counter, perm, kpos, (const T *)field, kforce, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+                           p->tile_info, p->n_tiles, p->counter, kv, rs, kpos, (const T *)field, kforce, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
     else
         hipLaunchKernelGGL((k_batch<T, MODE, false>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start,
-                           p->tile_info, p->n_tiles, p->counter, perm, kpos, (const T *)field, kforce, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+                           p->tile_info, p->n_tiles, p->counter, kv, rs, kpos, (const T *)field, kforce, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
     OT_HIP(hipGetLastError());
     if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
     if (p->ops_union & kOpSpread)
@@ -169,8 +173,15 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     if (dtype != OT_F32 && dtype != OT_F64) return fail(OT_ERR_INVALID, "dtype must be OT_F32 or OT_F64");
     if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
     const bool sort_points = tuning && (tuning->flags & OT_TUNE_SORT_POINTS);
-    int block = tuning && tuning->block ? tuning->block : 512;
-    int tile = tuning && tuning->tile ? tuning->tile : 4 * block;
+    // defaults: 512 threads and 4 points per thread, narrower and shorter
+    // tiles when there are too few points for two workgroups per CU
+    const int64_t want = 2 * (int64_t)tree->cus;
+    const int64_t n_all = offsets[n_inst] > 0 ? offsets[n_inst] : 0;
+    int block = 512;
+    while (block > 64 && (n_all + block - 1) / block < want) block >>= 1;
+    if (tuning && tuning->block) block = tuning->block;
+    int tile = (int)(block * std::max<int64_t>(1, std::min<int64_t>(4, n_all / ((int64_t)block * want))));
+    if (tuning && tuning->tile) tile = tuning->tile;
     if (block < 64 || block > 512 || block % 64) return fail(OT_ERR_INVALID, "block must be a multiple of 64 in [64, 512]");
     if (tile < block || tile % block || tile > (int)kCountMask) return fail(OT_ERR_INVALID, "tile must be a multiple of block");
     if (offsets[0] != 0) return fail(OT_ERR_INVALID, "offsets[0] must be 0");
@@ -223,13 +234,11 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
         while ((int64_t(1) << bits) <= tree->n_leaves) ++bits;   // keys go up to n_leaves
         p->sort_shift = std::max(0, bits - kSortKeyBits);
         p->sort_bits = bits - p->sort_shift;
-        const size_t vec = 3 * (size_t)n * (dtype == OT_F32 ? 4 : 8);
+        const size_t rec = ((ops_all & kOpSpread) ? 6 : 3) * (size_t)n * (dtype == OT_F32 ? 4 : 8);
         hipError_t e = hipSuccess;
         for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-            e = hipMalloc((void **)&p->skey[i], 4 * (size_t)n);
-            if (e == hipSuccess) e = hipMalloc((void **)&p->sval[i], 4 * (size_t)n);
-            if (e == hipSuccess) e = hipMalloc(&p->spos[i], vec);
-            if (e == hipSuccess && (ops_all & kOpSpread)) e = hipMalloc(&p->sforce[i], vec);
+            e = hipMalloc((void **)&p->skv[i], 8 * (size_t)n);
+            if (e == hipSuccess) e = hipMalloc(&p->srec[i], rec);
         }
         if (e == hipSuccess) e = hipMalloc(&p->sws, (size_t)point_sort_ws_bytes(n));
 
@@ -356,8 +365,7 @@ extern "C" int ot_batch_plan_destroy(ot_batch_plan *p)
     drop_graph(p);
     if (p->ev[0]) (void)hipEventDestroy(p->ev[0]);
     if (p->ev[1]) (void)hipEventDestroy(p->ev[1]);
-    for (void *q : {(void *)p->skey[0], (void *)p->skey[1], (void *)p->sval[0], (void *)p->sval[1], p->spos[0],
-                    p->spos[1], p->sforce[0], p->sforce[1], p->sws})
+    for (void *q : {(void *)p->skv[0], (void *)p->skv[1], p->srec[0], p->srec[1], p->sws})
         if (q) (void)hipFree(q);
     if (p->tile_start) (void)hipFree(p->tile_start);
     if (p->tile_info) (void)hipFree(p->tile_info);

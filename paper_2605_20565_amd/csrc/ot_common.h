@@ -175,6 +175,7 @@ int hip_fail(hipError_t e, const char *what);
 
 struct ot_tree {
     int device;
+    int cus;             // compute units of that device
     int32_t l_min, l_max, periodic;
     int64_t n_leaves;
     uint64_t *keys;      // sorted Morton keys

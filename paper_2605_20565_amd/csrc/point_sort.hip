@@ -1,15 +1,21 @@
 // Sorting the points of a batched run by host leaf, carrying their
-// positions, forces and original indices with them.
+// positions and forces with them.
 //
 // Neighbouring threads of the tracking pass then work on neighbouring host
 // cells: their stencil nodes share cache lines and the workgroup's spreading
-// table, and positions and forces are read with coalesced loads.  The key of a
-// point is its host leaf id; the passes order by bits [shift, shift + bits)
-// only (groups of 2^shift consecutive leaves, at most two 8-bit LSD passes),
-// and the tracking pass finishes the order inside each tile.  Each pass stages a
-// tile of 2048 keys in LDS with coalesced loads, ranks them stably by the
-// digit with eight 1-bit splits, and writes every digit's run contiguously;
-// the payload of a key is gathered from inside the tile and written once.
+// table, and positions and forces are read with coalesced loads.  Each point
+// is one 64-bit word host << 32 | input index plus one record of R values
+// (position, then force when spreading).  The passes order by key bits
+// [shift, shift + bits) only (groups of 2^shift consecutive leaves, at most
+// two 8-bit LSD passes).
+//
+// A pass takes tiles of 2048 points: the keys are staged in LDS with
+// coalesced loads, ranked stably by the digit with eight 1-bit splits, and
+// every digit's run is written contiguously; the record of a point is
+// gathered from inside the tile and written once.  (Tiles of 4096 and 8192
+// points give longer runs but fewer workgroups in flight, and were slower.)  The
+// first pass's digit counts come from the key kernel, and the first pass also
+// takes max |F| for the fixed-point scale, since it reads every force anyway.
 #include <hip/hip_runtime.h>
 
 #include "ot_common.h"
@@ -21,9 +27,15 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kItems = 8;
-constexpr int kTile = kThreads * kItems;
+constexpr int kTile = kThreads * kItems;   // 2048
 constexpr int kBits = 8;
 constexpr int kBuckets = 1 << kBits;
+static_assert(kThreads == kBuckets, "one digit per thread in the digit scan");
+
+// LDS index with one pad word per 32: the blocked reads (stride kItems) and
+// the striped writes both spread over the banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 5); }
+constexpr int kPadded = kTile + kTile / 32;
 
 __device__ __forceinline__ uint32_t exscan_256(uint32_t v, uint32_t *sh_w, uint32_t &total)
 {
@@ -48,22 +60,58 @@ __device__ __forceinline__ uint32_t exscan_256(uint32_t v, uint32_t *sh_w, uint3
     return pre + x - v;
 }
 
-// Host-leaf keys (and ids when asked) of all points.
-template <typename T>
-__global__ __launch_bounds__(256) void k_point_keys(TreeView tv, int64_t n, const T *__restrict__ pos,
-                                                    int32_t *__restrict__ ids, uint32_t *__restrict__ keys,
-                                                    uint32_t none)
+__device__ __forceinline__ unsigned long long abs_bits_of(float v)
 {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    uint32_t I[3];
-    const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
-    const uint32_t host = ok ? (descend(tv, I[0], I[1], I[2]) & kIdMask) : none;
-    if (ids) ids[k] = ok ? (int32_t)host : -1;
-    keys[k] = host;
+    return (unsigned long long)(__float_as_uint(v) & 0x7FFFFFFFu);
+}
+__device__ __forceinline__ unsigned long long abs_bits_of(double v)
+{
+    return (unsigned long long)__double_as_longlong(v) & 0x7FFFFFFFFFFFFFFFull;
 }
 
-__global__ __launch_bounds__(kThreads) void k_point_hist(const uint32_t *__restrict__ keys, int64_t n, int shift,
+// Block-wide max, one atomic per workgroup (same-address atomics serialise).
+__device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long long *sh, unsigned long long *out)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = std::max(v, (unsigned long long)__shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / 64; ++w) v = std::max(v, sh[w]);
+        if (v) atomicMax(out, v);
+    }
+}
+
+// Host leaf of every point (and ids when asked): kv = host << 32 | index,
+// points without a host get host = n_leaves.  Workgroup b covers the first
+// pass's tile b and leaves its digit counts in counts[d * nblocks + b].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n, const T *__restrict__ pos,
+                                                         int32_t *__restrict__ ids, uint64_t *__restrict__ kv,
+                                                         uint32_t none, int shift, uint32_t *__restrict__ counts,
+                                                         int nblocks)
+{
+    __shared__ uint32_t hist[kBuckets];
+    for (int i = threadIdx.x; i < kBuckets; i += kThreads) hist[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll 4
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t k = base + j * kThreads + threadIdx.x;
+        if (k < n) {
+            uint32_t I[3];
+            const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
+            const uint32_t host = ok ? (descend(tv, I[0], I[1], I[2]) & kIdMask) : none;
+            if (ids) ids[k] = ok ? (int32_t)host : -1;
+            kv[k] = ((uint64_t)host << 32) | (uint32_t)k;
+            atomicAdd(&hist[(host >> shift) & (kBuckets - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + blockIdx.x] = hist[d];
+}
+
+__global__ __launch_bounds__(kThreads) void k_point_hist(const uint64_t *__restrict__ kv, int64_t n, int shift,
                                                          uint32_t *__restrict__ counts, int nblocks)
 {
     __shared__ uint32_t hist[kBuckets];
@@ -72,36 +120,44 @@ __global__ __launch_bounds__(kThreads) void k_point_hist(const uint32_t *__restr
     const int64_t base = (int64_t)blockIdx.x * kTile;
     for (int j = threadIdx.x; j < kTile; j += kThreads) {
         const int64_t i = base + j;
-        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & (kBuckets - 1)], 1u);
+        if (i < n) atomicAdd(&hist[(uint32_t)(kv[i] >> (32 + shift)) & (kBuckets - 1)], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + blockIdx.x] = hist[d];
 }
 
-// One stable counting pass.  vin == nullptr: the values are the input
-// indices themselves (first pass).  fin may be null (no forces carried).
-template <typename T>
+// One stable counting pass over tiles of kTile points.  Records come from
+// rin (R values per point) or, in the first pass, from pos (3 per point) and
+// force (3 per point, R = 6 only).  maxbits != null: also max |F| over the
+// finite force components.
+template <typename T, int R>
 __global__ __launch_bounds__(kThreads) void k_point_scatter(
-    const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin, const T *__restrict__ pin,
-    const T *__restrict__ fin, uint32_t *__restrict__ kout, int32_t *__restrict__ vout, T *__restrict__ pout,
-    T *__restrict__ fout, int64_t n, int shift, const uint32_t *__restrict__ offs, int nblocks)
+    const uint64_t *__restrict__ kin, const T *__restrict__ rin, const T *__restrict__ pos,
+    const T *__restrict__ force, uint64_t *__restrict__ kout, T *__restrict__ rout, int64_t n, int shift,
+    const uint32_t *__restrict__ offs, int nblocks, unsigned long long *__restrict__ maxbits)
 {
-    __shared__ uint32_t sk[kTile];
-    __shared__ uint16_t si[kTile];
+    __shared__ uint32_t sk[kPadded];
+    __shared__ uint16_t si[kPadded];
     __shared__ uint32_t sh_w[kThreads / 64];
     __shared__ uint32_t dstart[kBuckets];
     __shared__ uint32_t dcount[kBuckets];
+    __shared__ unsigned long long sh_max[kThreads / 64];
 
     const int64_t base = (int64_t)blockIdx.x * kTile;
     const int64_t rem = n - base;
     const int valid = rem < kTile ? (int)rem : kTile;
     for (int d = threadIdx.x; d < kBuckets; d += kThreads) dcount[d] = 0;
+    __syncthreads();
     // coalesced load of the tile's keys; padding sorts last
-#pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int li = j * kThreads + threadIdx.x;
-        sk[li] = li < valid ? kin[base + li] : 0xFFFFFFFFu;
-        si[li] = (uint16_t)li;
+        uint32_t key = 0xFFFFFFFFu;
+        if (li < valid) {
+            key = (uint32_t)(kin[base + li] >> 32);
+            atomicAdd(&dcount[(key >> shift) & (kBuckets - 1)], 1u);
+        }
+        sk[pad(li)] = key;
+        si[pad(li)] = (uint16_t)li;
     }
     __syncthreads();
     uint32_t k[kItems];
@@ -109,9 +165,8 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     const int t0 = threadIdx.x * kItems;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        k[j] = sk[t0 + j];
-        x[j] = si[t0 + j];
-        if (t0 + j < valid) atomicAdd(&dcount[(k[j] >> shift) & (kBuckets - 1)], 1u);
+        k[j] = sk[pad(t0 + j)];
+        x[j] = si[pad(t0 + j)];
     }
     __syncthreads();
     for (int b = 0; b < kBits; ++b) {
@@ -126,48 +181,84 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
             const uint32_t g = (uint32_t)(t0 + j);
             const uint32_t p = bit ? total_zeros + (g - zb) : zb;
             zb += 1u - bit;
-            sk[p] = k[j];
-            si[p] = (uint16_t)x[j];
+            sk[pad((int)p)] = k[j];
+            si[pad((int)p)] = (uint16_t)x[j];
         }
         __syncthreads();
         if (b + 1 < kBits) {
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
-                k[j] = sk[t0 + j];
-                x[j] = si[t0 + j];
+                k[j] = sk[pad(t0 + j)];
+                x[j] = si[pad(t0 + j)];
             }
             __syncthreads();
         }
     }
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int d = 0; d < kBuckets; ++d) {
-            dstart[d] = acc;
-            acc += dcount[d];
-        }
+    {
+        uint32_t tot;
+        const uint32_t c = dcount[threadIdx.x];
+        dstart[threadIdx.x] = exscan_256(c, sh_w, tot);
     }
     __syncthreads();
-    // coalesced write: sorted position i -> its digit's run; payload gathered from the tile
-#pragma unroll
+    // coalesced writes: sorted position i goes to its digit's run; the record
+    // is gathered from inside the tile
+    unsigned long long mx = 0;
     for (int j = 0; j < kItems; ++j) {
         const int i = j * kThreads + threadIdx.x;
         if (i < valid) {
-            const uint32_t key = sk[i];
-            const int64_t src = base + si[i];
+            const uint32_t key = sk[pad(i)];
+            const int64_t src = base + si[pad(i)];
             const uint32_t d = (key >> shift) & (kBuckets - 1);
             const int64_t dst = (int64_t)offs[(int64_t)d * nblocks + blockIdx.x] + (i - (int)dstart[d]);
-            kout[dst] = key;
-            vout[dst] = vin ? vin[src] : (int32_t)src;
-            pout[3 * dst] = pin[3 * src];
-            pout[3 * dst + 1] = pin[3 * src + 1];
-            pout[3 * dst + 2] = pin[3 * src + 2];
-            if (fin) {
-                fout[3 * dst] = fin[3 * src];
-                fout[3 * dst + 1] = fin[3 * src + 1];
-                fout[3 * dst + 2] = fin[3 * src + 2];
+            kout[dst] = ((uint64_t)key << 32) | (uint32_t)kin[src];
+            T v[R];
+            if (rin) {
+#pragma unroll
+                for (int c = 0; c < R; ++c) v[c] = rin[R * src + c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] = pos[3 * src + c];
+#pragma unroll
+                for (int c = 3; c < R; ++c) v[c] = force[3 * src + (c - 3)];
+            }
+#pragma unroll
+            for (int c = 0; c < R; ++c) rout[R * dst + c] = v[c];
+            if (maxbits) {
+#pragma unroll
+                for (int c = 3; c < R; ++c)
+                    if (isfinite(v[c])) mx = std::max(mx, abs_bits_of(v[c]));
             }
         }
     }
+    if (maxbits) block_max_to(mx, sh_max, maxbits);
+}
+
+template <typename T, int R>
+void sort_passes(const TreeView &tv, int64_t n, int64_t n_leaves, int shift, int bits, const T *pos, const T *force,
+                 int32_t *ids, PointSortBufs<T> &b, unsigned long long *maxbits, hipStream_t s,
+                 PointSortResult<T> &out)
+{
+    const int nb = (int)((n + kTile - 1) / kTile);
+    const int64_t nc = (int64_t)kBuckets * nb;
+    uint32_t *counts = (uint32_t *)b.ws, *offs = counts + nc, *tmp = offs + nc;
+    hipLaunchKernelGGL(k_point_keys<T>, dim3(nb), dim3(kThreads), 0, s, tv, n, pos, ids, b.kv[0],
+                       (uint32_t)n_leaves, shift, counts, nb);
+    const uint64_t *kin = b.kv[0];
+    const T *rin = nullptr;
+    int cur = 0;
+    for (int sh = 0; sh < bits; sh += kBits) {
+        const int o = cur ^ 1;   // write buffer: 1, 0, 1, ...
+        if (sh > 0) hipLaunchKernelGGL(k_point_hist, dim3(nb), dim3(kThreads), 0, s, kin, n, shift + sh, counts, nb);
+        exclusive_scan(counts, offs, nc, tmp, s);
+        hipLaunchKernelGGL((k_point_scatter<T, R>), dim3(nb), dim3(kThreads), 0, s, kin, rin, pos, force, b.kv[o],
+                           b.rec[o], n, shift + sh, (const uint32_t *)offs, nb,
+                           sh == 0 ? maxbits : (unsigned long long *)nullptr);
+        kin = b.kv[o];
+        rin = b.rec[o];
+        cur = o;
+    }
+    out.kv = kin;
+    out.rec = rin;
 }
 
 }  // namespace
@@ -181,38 +272,18 @@ int64_t point_sort_ws_bytes(int64_t n)
 
 template <typename T>
 void point_sort(const TreeView &tv, int64_t n, int64_t n_leaves, int shift, int bits, const T *pos, const T *force,
-                int32_t *ids, PointSortBufs<T> &b, hipStream_t s, PointSortResult<T> &out)
+                int32_t *ids, PointSortBufs<T> &b, unsigned long long *maxbits, hipStream_t s,
+                PointSortResult<T> &out)
 {
-    const unsigned gb = (unsigned)((n + 255) / 256);
-    hipLaunchKernelGGL(k_point_keys<T>, dim3(gb), dim3(256), 0, s, tv, n, pos, ids, b.key[0], (uint32_t)n_leaves);
-    const int nb = (int)((n + kTile - 1) / kTile);
-    const int64_t nc = (int64_t)kBuckets * nb;
-    uint32_t *counts = (uint32_t *)b.ws, *offs = counts + nc, *tmp = offs + nc;
-    const uint32_t *kin = b.key[0];
-    const int32_t *vin = nullptr;
-    const T *pin = pos, *fin = force;
-    int cur = 0;
-    for (int sh = 0; sh < bits; sh += kBits) {
-        const int o = cur ^ 1;   // write buffer: 1, 0, 1, ...
-        hipLaunchKernelGGL(k_point_hist, dim3(nb), dim3(kThreads), 0, s, kin, n, shift + sh, counts, nb);
-        exclusive_scan(counts, offs, nc, tmp, s);
-        hipLaunchKernelGGL(k_point_scatter<T>, dim3(nb), dim3(kThreads), 0, s, kin, vin, pin, fin, b.key[o], b.val[o],
-                           b.pos[o], force ? b.force[o] : (T *)nullptr, n, shift + sh, (const uint32_t *)offs, nb);
-        kin = b.key[o];
-        vin = b.val[o];
-        pin = b.pos[o];
-        fin = force ? b.force[o] : nullptr;
-        cur = o;
-    }
-    out.host = kin;
-    out.perm = vin;
-    out.pos = pin;
-    out.force = fin;
+    if (force) sort_passes<T, 6>(tv, n, n_leaves, shift, bits, pos, force, ids, b, maxbits, s, out);
+    else sort_passes<T, 3>(tv, n, n_leaves, shift, bits, pos, nullptr, ids, b, nullptr, s, out);
+    out.stride = force ? 6 : 3;
 }
 
 template void point_sort<float>(const TreeView &, int64_t, int64_t, int, int, const float *, const float *, int32_t *,
-                                PointSortBufs<float> &, hipStream_t, PointSortResult<float> &);
+                                PointSortBufs<float> &, unsigned long long *, hipStream_t, PointSortResult<float> &);
 template void point_sort<double>(const TreeView &, int64_t, int64_t, int, int, const double *, const double *,
-                                 int32_t *, PointSortBufs<double> &, hipStream_t, PointSortResult<double> &);
+                                 int32_t *, PointSortBufs<double> &, unsigned long long *, hipStream_t,
+                                 PointSortResult<double> &);
 
 }  // namespace ot

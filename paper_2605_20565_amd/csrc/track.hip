@@ -36,11 +36,11 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
         LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
         sink.clear();
         __syncthreads();
-        track_range<T, OPS, PER>(tv, start, end, nullptr, pos, field, force, ids, vel, sink);
+        track_range<T, OPS, PER>(tv, start, end, nullptr, 3, pos, field, force, ids, vel, sink);
         sink.flush();
     } else {
         DirectSink<T, MODE> sink{fout, facc, 0.0};
-        track_range<T, OPS, PER>(tv, start, end, nullptr, pos, field, force, ids, vel, sink);
+        track_range<T, OPS, PER>(tv, start, end, nullptr, 3, pos, field, force, ids, vel, sink);
     }
 }
 
@@ -54,16 +54,15 @@ __global__ __launch_bounds__(256) void k_grad(TreeView tv, int64_t n, const T *_
     grad_point<T>(tv, k, pos, field, vec, grad);
 }
 
-constexpr int kPointsPerThread = 4;
+constexpr int kMaxPointsPerThread = 4;
 
 template <typename T, int MODE>
-int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, hipStream_t s, int64_t n, const void *pos,
+int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStream_t s, int64_t n, const void *pos,
                  const void *field, const void *force, int32_t *ids, void *vel, void *fout)
 {
     const T *P = (const T *)pos, *Fd = (const T *)field, *Fo = (const T *)force;
     T *V = (T *)vel, *O = (T *)fout;
     const FxState *fx = (const FxState *)t->scratch;
-    const int64_t tile = (int64_t)b.x * kPointsPerThread;
 #define OT_LAUNCH(OPSV)                                                                                         \
     if (t->view.periodic)                                                                                        \
         hipLaunchKernelGGL((k_track<T, OPSV, MODE, true>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,    \
@@ -90,8 +89,7 @@ int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, hipStream_t s, int64
 
 // Prepare the spreading target before a pass: zero the output (atomic mode,
 // overwrite) or the fixed-point accumulators and compute the scale.
-int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const void *force, int64_t n,
-                    void *fout, hipStream_t s)
+int spread_begin(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s)
 {
     const int64_t n3 = t->n_leaves * 3;
     FxState *fx = (FxState *)t->scratch;
@@ -103,19 +101,34 @@ int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const
     } else {
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1024), dim3(256), 0, s, t->fx_acc, n3, 0ull);
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &fx->maxbits, (int64_t)1, 0ull);
-        const int64_t m = n * 3;
-        if (m > 0) {
-            unsigned gb = (unsigned)std::min<int64_t>((m + 1023) / 1024, 1024);
-            if (dtype == OT_F32)
-                hipLaunchKernelGGL(k_maxabs<float>, dim3(gb), dim3(256), 0, s, (const float *)force, m, &fx->maxbits);
-            else
-                hipLaunchKernelGGL(k_maxabs<double>, dim3(gb), dim3(256), 0, s, (const double *)force, m, &fx->maxbits);
-        }
-        if (dtype == OT_F32) hipLaunchKernelGGL(k_fx_prepare<float>, dim3(1), dim3(64), 0, s, fx, n);
-        else hipLaunchKernelGGL(k_fx_prepare<double>, dim3(1), dim3(64), 0, s, fx, n);
     }
     OT_HIP(hipGetLastError());
     return OT_OK;
+}
+
+int spread_scale(const ot_tree *t, int dtype, int mode, const void *force, int64_t n, hipStream_t s)
+{
+    if (mode != OT_SPREAD_FIXED) return OT_OK;
+    FxState *fx = (FxState *)t->scratch;
+    const int64_t m = force ? n * 3 : 0;
+    if (m > 0) {
+        unsigned gb = (unsigned)std::min<int64_t>((m + 1023) / 1024, 1024);
+        if (dtype == OT_F32)
+            hipLaunchKernelGGL(k_maxabs<float>, dim3(gb), dim3(256), 0, s, (const float *)force, m, &fx->maxbits);
+        else
+            hipLaunchKernelGGL(k_maxabs<double>, dim3(gb), dim3(256), 0, s, (const double *)force, m, &fx->maxbits);
+    }
+    if (dtype == OT_F32) hipLaunchKernelGGL(k_fx_prepare<float>, dim3(1), dim3(64), 0, s, fx, n);
+    else hipLaunchKernelGGL(k_fx_prepare<double>, dim3(1), dim3(64), 0, s, fx, n);
+    OT_HIP(hipGetLastError());
+    return OT_OK;
+}
+
+int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const void *force, int64_t n,
+                    void *fout, hipStream_t s)
+{
+    int rc = spread_begin(t, dtype, mode, accumulate, fout, s);
+    return rc ? rc : spread_scale(t, dtype, mode, force, n, s);
 }
 
 int spread_epilogue(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s)
@@ -156,15 +169,22 @@ int track(const ot_tree *t, int ops, const void *field, const void *force, const
         if ((rc = spread_prologue(t, dtype, mode, accumulate, force, n, fout, s))) return rc;
     }
     if (n > 0) {
-        const int threads = (ops & kOpSpread) ? 512 : 256;
-        const int64_t tile = (int64_t)threads * kPointsPerThread;
+        // Enough workgroups to give every CU two, when there are points for
+        // them: small sets get narrower workgroups and one point per thread
+        // (their time is latency, not throughput); large ones up to
+        // kMaxPointsPerThread points per thread.
+        const int64_t want = 2 * (int64_t)t->cus;
+        int threads = (ops & kOpSpread) ? 512 : 256;
+        while (threads > 64 && (n + threads - 1) / threads < want) threads >>= 1;
+        const int64_t ppt = std::max<int64_t>(1, std::min<int64_t>(kMaxPointsPerThread, n / ((int64_t)threads * want)));
+        const int64_t tile = (int64_t)threads * ppt;
         dim3 b(threads), g((unsigned)((n + tile - 1) / tile));
         if (dtype == OT_F32)
-            rc = mode == OT_SPREAD_FIXED ? dispatch_ops<float, kModeFixed>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout)
-                                         : dispatch_ops<float, kModeAtomic>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout);
+            rc = mode == OT_SPREAD_FIXED ? dispatch_ops<float, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout)
+                                         : dispatch_ops<float, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout);
         else
-            rc = mode == OT_SPREAD_FIXED ? dispatch_ops<double, kModeFixed>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout)
-                                         : dispatch_ops<double, kModeAtomic>(ops, t, g, b, s, n, pos, field, force, ids, vel, fout);
+            rc = mode == OT_SPREAD_FIXED ? dispatch_ops<double, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout)
+                                         : dispatch_ops<double, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout);
         if (rc) return rc;
         OT_HIP(hipGetLastError());
     }

@@ -273,16 +273,19 @@ struct LdsSink {
     }
 };
 
+// Point k: position pos[rs k + 0..2], force force[rs k + 0..2] (rs = 3 for
+// the caller's arrays, the record stride for sorted records).  With kv
+// (sorted points: host << 32 | input index) the per-point outputs go to the
+// input index.
 template <typename T, int OPS, bool PER, typename Sink>
-__device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const int32_t *__restrict__ perm,
+__device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const uint64_t *__restrict__ kv, int rs,
                                             const T *__restrict__ pos, const T *__restrict__ field,
                                             const T *__restrict__ force, int32_t *__restrict__ ids,
                                             T *__restrict__ vel, Sink &sink)
 {
-    // With a permutation, positions and forces are already in sorted order
-    // (index k) and the per-point outputs go to the input index perm[k].
-    const int64_t kd = perm ? (int64_t)perm[k] : k;
-    const T X[3] = {pos[3 * k], pos[3 * k + 1], pos[3 * k + 2]};
+    const int64_t kd = kv ? (int64_t)(uint32_t)kv[k] : k;
+    const int64_t kp = (int64_t)rs * k;
+    const T X[3] = {pos[kp], pos[kp + 1], pos[kp + 2]};
     uint32_t I[3];
     const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
     const uint32_t e = ok ? descend(tv, I[0], I[1], I[2]) : 0u;
@@ -337,7 +340,7 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
             // sink the interpolation sums below the spreading and keep all
             // 27 gathered values alive through it
             if (OPS & kOpInterp) asm volatile("" : "+v"(U[0]), "+v"(U[1]), "+v"(U[2]));
-            const T F[3] = {force[3 * k], force[3 * k + 1], force[3 * k + 2]};
+            const T F[3] = {force[kp], force[kp + 1], force[kp + 2]};
             uint32_t live = (1u << 27) - 1u;
             if (!PER) {
 #pragma unroll
@@ -485,12 +488,12 @@ __global__ void k_fx_finalize(const unsigned long long *__restrict__ acc, T *__r
 // Process points [start, end) of one tile with all threads of the workgroup.
 template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, int64_t end,
-                                            const int32_t *__restrict__ perm, const T *__restrict__ pos,
+                                            const uint64_t *__restrict__ kv, int rs, const T *__restrict__ pos,
                                             const T *__restrict__ field, const T *__restrict__ force,
                                             int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink)
 {
     for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x)
-        track_point<T, OPS, PER, Sink>(tv, k, perm, pos, field, force, ids, vel, sink);
+        track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink);
 }
 
 // LDS table size of the aggregating sink, per precision and mode

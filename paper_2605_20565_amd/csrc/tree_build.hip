@@ -525,6 +525,9 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
 
     ot_tree *tr = new ot_tree();
     OT_HIP(hipGetDevice(&tr->device));
+    tr->cus = 0;
+    (void)hipDeviceGetAttribute(&tr->cus, hipDeviceAttributeMultiprocessorCount, tr->device);
+    if (tr->cus <= 0) tr->cus = 1;
     tr->l_min = l_min;
     tr->l_max = L;
     tr->periodic = tv.periodic;

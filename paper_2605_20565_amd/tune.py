@@ -35,8 +35,10 @@ class Candidate:
 def default_candidates(n_points: int, uniform_ops: bool = True) -> List[Candidate]:
     sorts = (True, False) if uniform_ops else (False,)
     out = []
+    # small runs are latency bound: narrow workgroups keep every CU busy
+    blocks = (64, 128, 256, 512) if n_points < 2 * 256 * 512 else (256, 512)
     for sort in sorts:
-        for block in (256, 512):
+        for block in blocks:
             for mult in (1, 2, 4, 8):
                 tile = block * mult
                 if tile > max(block, n_points) or (sort and mult == 8) or (not sort and mult == 1):
