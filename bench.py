@@ -338,6 +338,9 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
         for o in outs[1:])
     del outs
 
+    # multi-direct forcing (5 iterations) on the workload's bubble markers
+    res["mdf"] = mdf_measure(w, tree, field, dev, dt, args.mode, torch, timeit)
+
     # launch latency on the small workload 1 (11k points; latency bound, so no roofline figure)
     res["config1_latency_us"] = config1_latency(dev, dt, args.mode, ot, torch, timeit)
 
@@ -351,6 +354,26 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
     # error against the oracle on a sample of the same inputs
     res["error_vs_oracle"] = oracle_check(w, tree, dev, dt, torch)
     return res
+
+
+def mdf_measure(w, tree, field, dev, dt, mode, torch, timeit, n_iter=5):
+    idx = [i for i, k in enumerate(w.kinds) if k == "markers"]
+    if not idx:
+        return None
+    sel = np.concatenate([np.arange(w.instances[i], w.instances[i + 1]) for i in idx])
+    P = torch.from_numpy(np.ascontiguousarray(w.points[sel])).to(dev, dt)
+    tgt = torch.zeros_like(P)   # bodies at rest: the forcing drives the slip to zero
+    u = field.clone()
+    work = torch.empty(max(1, int(tree_mdf_bytes(tree, P))), dtype=torch.uint8, device=dev)
+    ms = timeit(lambda: tree.mdf(u, P, tgt, n_iter, mode=mode, inplace=True, work=work), 10)
+    return {"markers": int(P.shape[0]), "iterations": n_iter, "ms_per_step": round(ms, 4),
+            "ms_per_iteration": round(ms / n_iter, 4), "spread_mode": mode}
+
+
+def tree_mdf_bytes(tree, P):
+    import paper_2605_20565_amd as ot
+    code = ot.OT_F32 if P.dtype.itemsize == 4 else ot.OT_F64
+    return ot.lib.ot_mdf_workspace_bytes(tree._h, P.shape[0], code)
 
 
 def config1_latency(dev, dt, mode, ot, torch, timeit):

@@ -185,6 +185,25 @@ int ot_track(const ot_tree *tree, int32_t ops, const void *field, const void *fo
 int ot_grad_pos(const ot_tree *tree, const void *field, const void *vec, const void *pos,
                 int32_t dtype, int64_t n, void *grad, void *stream);
 
+/* Multi-direct forcing of the immersed-boundary method (IBM subsection of
+ * Sec. 2.2), n_iter iterations of:
+ *   u_k = interpolate(field) at the markers pos,
+ *   F_k = (target_k - u_k) / dt,
+ *   f   = spread(F_k) to the leaves (mode: OT_SPREAD_ATOMIC or FIXED),
+ *   field += f / rho.
+ * field: (n_leaves, 3), updated in place.  pos, target: (n, 3) markers and
+ * their prescribed velocities.  force_lag (nullable, (n, 3)) receives the
+ * sum over the iterations of F_k, force_eul (nullable, (n_leaves, 3)) the sum
+ * of f (the total forcing of the time step).  work: caller-owned device
+ * buffer of ot_mdf_workspace_bytes(tree, n, dtype) bytes; the call allocates
+ * nothing.  Uses the tree's spreading workspace in FIXED mode (calls on one
+ * tree must not run concurrently).  Errors: OT_ERR_INVALID (null arrays,
+ * n < 0, n_iter < 0, dt or rho not positive, bad mode/dtype), OT_ERR_HIP. */
+int64_t ot_mdf_workspace_bytes(const ot_tree *tree, int64_t n, int32_t dtype);
+int ot_mdf(const ot_tree *tree, void *field, const void *pos, const void *target, int32_t dtype,
+           int64_t n, int32_t n_iter, double dt, double rho, int32_t mode, void *force_lag,
+           void *force_eul, void *work, void *stream);
+
 /* Batched pass over many point sets of uneven size (bubbles' markers and
  * particle groups) in one persistent launch captured in a HIP graph.
  * offsets: host (n_inst + 1,) int64, ascending, offsets[0] = 0; instance i

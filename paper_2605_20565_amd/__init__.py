@@ -56,7 +56,7 @@ OT_TUNE_SORT_POINTS = 1
 EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_get", "ot_tree_leaves",
            "ot_locate", "ot_interpolate", "ot_spread", "ot_track", "ot_grad_pos", "ot_batch_plan_create",
            "ot_batch_run", "ot_batch_plan_shape", "ot_batch_plan_timing", "ot_batch_last_kernel_ms",
-           "ot_batch_plan_destroy", "ot_strerror", "ot_last_error")
+           "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes")
 
 
 def _load():
@@ -82,11 +82,14 @@ def _load():
         "ot_batch_plan_timing": [P, i32],
         "ot_batch_last_kernel_ms": [P, ctypes.POINTER(ctypes.c_float)],
         "ot_batch_plan_destroy": [P],
+        "ot_mdf": [P, P, P, P, i32, i64, i32, ctypes.c_double, ctypes.c_double, i32, P, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    L.ot_mdf_workspace_bytes.argtypes = [P, i64, i32]
+    L.ot_mdf_workspace_bytes.restype = i64
     L.ot_strerror.argtypes = [i32]
     L.ot_strerror.restype = ctypes.c_char_p
     L.ot_last_error.argtypes = []
@@ -285,6 +288,30 @@ class Tree:
         _check(lib.ot_grad_pos(self._h, _ptr(field), _ptr(vec), _ptr(pos), _dtype_code(pos), pos.shape[0],
                                _ptr(g), _stream()))
         return g
+
+    def mdf(self, field: torch.Tensor, pos: torch.Tensor, target: torch.Tensor, n_iter: int, dt: float = 1.0,
+            rho: float = 1.0, mode: str = "fixed", inplace: bool = False,
+            work: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+        """Multi-direct forcing (ot_mdf): returns (field, force_lag, force_eul).
+        With inplace=True `field` itself is updated and returned."""
+        pos = _rows3(pos, "pos")
+        target = _rows3(target, "target")
+        field = _rows3(field, "field")
+        if field.shape[0] != self.n_leaves or target.shape[0] != pos.shape[0]:
+            raise ValueError("field must be (n_leaves, 3) and target (n, 3)")
+        if field.dtype != pos.dtype or target.dtype != pos.dtype:
+            raise ValueError("field, target and pos must share a dtype")
+        mcode = _mode_code(mode)
+        u = field if inplace else field.clone()
+        n = pos.shape[0]
+        f_lag = torch.empty_like(pos)
+        f_eul = torch.empty_like(u)
+        nbytes = int(lib.ot_mdf_workspace_bytes(self._h, n, _dtype_code(pos)))
+        if work is None or work.numel() * work.element_size() < nbytes or work.device != pos.device:
+            work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=pos.device)
+        _check(lib.ot_mdf(self._h, _ptr(u), _ptr(pos), _ptr(target), _dtype_code(pos), n, int(n_iter),
+                          float(dt), float(rho), mcode, _ptr(f_lag), _ptr(f_eul), _ptr(work), _stream()))
+        return u, f_lag, f_eul
 
 
 class BatchPlan:

@@ -59,3 +59,10 @@ def test_strerror_and_host_side_validation(ot):
     off = (ctypes.c_int64 * 2)(0, 5)
     ops = (ctypes.c_int32 * 1)(7)
     assert L.ot_batch_plan_create(None, off, ops, 1, 0, 0, None, ctypes.byref(h)) == -1
+
+
+def test_mdf_host_side_validation(ot):
+    L = ot.lib
+    assert L.ot_mdf_workspace_bytes(None, 10, 0) == -1
+    assert L.ot_mdf(None, None, None, None, 0, 10, 3, 1.0, 1.0, 1, None, None, None, None) == -1
+    assert b"tree is NULL" in L.ot_last_error()

@@ -1,0 +1,122 @@
+"""GPU multi-direct forcing (ot_mdf) against the FP64 oracle.
+
+The oracle is the plain composition of its interpolation and spreading in the
+order of the IBM subsection of Sec. 2.2 (oracle/ibm.py).  Errors compound over
+the iterations, so the bound is stated against the size of what the
+iterations add: |got - want| <= 10 * tol * scale with tol = 1e-12 (FP64) or
+1e-5 (FP32) and scale = max|u0| + sum over iterations of max|f|/rho for the
+velocity (max|F_k| summed for the marker force, max|f| summed for the leaf
+force).  The closed-form slip decay (factor 1 - 1/(8 dt rho) per iteration
+for a lone marker on a uniform grid) is checked directly, and FIXED mode must
+be bitwise independent of the marker order.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import TOL, as_dtype, gpu_tree, oracle_tree, to_dev
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32]
+
+
+@pytest.fixture(scope="module")
+def ot():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2605_20565_amd as m
+    return m
+
+
+def _ibm():
+    from oracle import ibm
+    return ibm
+
+
+def _rigid_targets(pos, centre, omega=(0.3, -0.2, 1.0), v=(0.1, 0.0, -0.05)):
+    r = pos - np.asarray(centre)
+    return np.asarray(v) + np.cross(np.asarray(omega), r)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("mode", ["atomic", "fixed"])
+def test_mdf_matches_oracle_workload1(ot, dtype, mode):
+    w = synth.workload(1)
+    markers = w.points[:w.instances[1]]                 # the sphere's markers (instance 0)
+    sph = w.spheres[0]
+    pos = as_dtype(markers, dtype)
+    target = as_dtype(_rigid_targets(markers, sph.centre), dtype)
+    o = oracle_tree(w.tree)
+    field = as_dtype(o.permute_rows(w.field), dtype)
+    n_iter, dt, rho = 5, 1.0, 1.0
+    u_o, fl_o, fe_o = _ibm().mdf(o, field, pos, target, n_iter, dt, rho)
+    # scales: what the iterations add
+    u = field.copy()
+    s_u, s_fl, s_fe = np.abs(field).max(), 0.0, 0.0
+    for _ in range(n_iter):
+        Fk = (target - o.interpolate(u, pos)) / dt
+        f = o.spread(Fk, pos)
+        u = u + f / rho
+        s_u += np.abs(f).max() / rho
+        s_fl += np.abs(Fk).max()
+        s_fe += np.abs(f).max()
+    t = gpu_tree(w.tree)
+    ug, flg, feg = t.mdf(to_dev(field, dtype), to_dev(pos, dtype), to_dev(target, dtype), n_iter, dt, rho, mode=mode)
+    tol = 10 * TOL[dtype]
+    assert np.abs(ug.cpu().double().numpy() - u_o).max() <= tol * s_u
+    assert np.abs(flg.cpu().double().numpy() - fl_o).max() <= tol * s_fl
+    assert np.abs(feg.cpu().double().numpy() - fe_o).max() <= tol * s_fe
+    # the forcing did its job: the slip shrank
+    slip0 = np.abs(target - o.interpolate(field, pos)).max()
+    slip = np.abs(target - o.interpolate(ug.cpu().double().numpy(), pos)).max()
+    assert slip < 0.7 * slip0
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("mode", ["atomic", "fixed"])
+def test_mdf_lone_marker_closed_form(ot, dtype, mode):
+    spec = synth.uniform_tree(5, seed=4)
+    o = oracle_tree(spec)
+    t = gpu_tree(spec)
+    rng = np.random.default_rng(9)
+    pos = as_dtype(rng.random((1, 3)), dtype)
+    field = as_dtype(rng.standard_normal((t.n_leaves, 3)), dtype)
+    target = np.array([[1.0, -2.0, 0.5]])
+    dt, rho = 2.0, 1.5
+    q = 1.0 - 1.0 / (8.0 * dt * rho)
+    slip0 = target - o.interpolate(field, pos)
+    rt = 1e-10 if dtype == torch.float64 else 2e-5
+    for m in (1, 3, 6):
+        ug, _, _ = t.mdf(to_dev(field, dtype), to_dev(pos, dtype), to_dev(target, dtype), m, dt, rho, mode=mode)
+        slip = target - o.interpolate(ug.cpu().double().numpy(), pos)
+        np.testing.assert_allclose(slip, slip0 * q ** m, rtol=rt, atol=rt * np.abs(slip0).max())
+
+
+def test_mdf_fixed_independent_of_marker_order(ot):
+    w = synth.workload(1)
+    markers = w.points[:w.instances[1]]
+    dtype = torch.float32
+    pos = as_dtype(markers, dtype)
+    target = as_dtype(_rigid_targets(markers, w.spheres[0].centre), dtype)
+    t = gpu_tree(w.tree)
+    field = to_dev(as_dtype(oracle_tree(w.tree).permute_rows(w.field), dtype), dtype)
+    perm = np.random.default_rng(3).permutation(pos.shape[0])
+    ua, fla, fea = t.mdf(field, to_dev(pos, dtype), to_dev(target, dtype), 4, mode="fixed")
+    ub, flb, feb = t.mdf(field, to_dev(pos[perm], dtype), to_dev(target[perm], dtype), 4, mode="fixed")
+    assert torch.equal(ua.view(torch.int32), ub.view(torch.int32))
+    assert torch.equal(fea.view(torch.int32), feb.view(torch.int32))
+    assert torch.equal(fla[torch.from_numpy(perm).cuda()].view(torch.int32), flb.view(torch.int32))
+
+
+def test_mdf_inplace_and_zero_iterations(ot):
+    spec = synth.uniform_tree(3, seed=0)
+    t = gpu_tree(spec)
+    field = torch.randn((t.n_leaves, 3), dtype=torch.float64, device="cuda")
+    keep = field.clone()
+    pos = torch.tensor([[0.3, 0.4, 0.5]], dtype=torch.float64, device="cuda")
+    tgt = torch.ones((1, 3), dtype=torch.float64, device="cuda")
+    u, fl, fe = t.mdf(field, pos, tgt, 0)
+    assert torch.equal(u, keep) and not fl.any() and not fe.any()
+    u, _, _ = t.mdf(field, pos, tgt, 2, inplace=True)
+    assert u.data_ptr() == field.data_ptr() and not torch.equal(field, keep)
