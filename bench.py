@@ -366,8 +366,15 @@ def mdf_measure(w, tree, field, dev, dt, mode, torch, timeit, n_iter=5):
     u = field.clone()
     work = torch.empty(max(1, int(tree_mdf_bytes(tree, P))), dtype=torch.uint8, device=dev)
     ms = timeit(lambda: tree.mdf(u, P, tgt, n_iter, mode=mode, inplace=True, work=work), 10)
+    # the bodies' IBM force and torque from the marker forces (per-body sums)
+    import paper_2605_20565_amd as ot
+    _, f_lag, _ = tree.mdf(u, P, tgt, n_iter, mode=mode, work=work)
+    offs = np.concatenate([[0], np.cumsum([w.instances[i + 1] - w.instances[i] for i in idx])])
+    cen = torch.tensor([w.spheres[i].centre for i in range(len(idx))], dtype=dt, device=dev)
+    us = timeit(lambda: ot.body_sums(f_lag, P, offs, cen, 1.0), 20) * 1e3
     return {"markers": int(P.shape[0]), "iterations": n_iter, "ms_per_step": round(ms, 4),
-            "ms_per_iteration": round(ms / n_iter, 4), "spread_mode": mode}
+            "ms_per_iteration": round(ms / n_iter, 4), "spread_mode": mode,
+            "body_force_torque_us": round(us, 1), "bodies": len(idx)}
 
 
 def tree_mdf_bytes(tree, P):

@@ -200,6 +200,23 @@ int ot_grad_pos(const ot_tree *tree, const void *field, const void *vec, const v
  * tree must not run concurrently).  Errors: OT_ERR_INVALID (null arrays,
  * n < 0, n_iter < 0, dt or rho not positive, bad mode/dtype), OT_ERR_HIP. */
 int64_t ot_mdf_workspace_bytes(const ot_tree *tree, int64_t n, int32_t dtype);
+
+/* Per-body sums of the IBM coupling (Sec. 2.3, fully resolved bodies).  For
+ * body b = 0..n_body-1, owning points [offsets[b], offsets[b+1]):
+ *   sum_out[b]    = sum_k vec_k dV_k,
+ *   moment_out[b] = sum_k (pos_k - centres[b]) x vec_k dV_k,
+ * with pos_k - centres[b] taken as the nearest periodic image when
+ * periodic != 0 (unit cube).  With vec = marker forces these are minus the
+ * IBM force and torque on the body; with vec = velocity interpolated at
+ * points inside the body, the enclosed fluid's linear and angular momentum
+ * divided by rho_f.  vec, pos: (n, 3) dtype; offsets: device (n_body + 1,)
+ * int64, ascending (segments are clamped to [0, n]); centres: (n_body, 3)
+ * dtype; dv: (n,) dtype, or NULL to use dv_all for every point.  Outputs are
+ * FP64 (n_body, 3), summed in FP64 in a fixed order (bitwise reproducible).
+ * Errors: OT_ERR_INVALID, OT_ERR_HIP. */
+int ot_body_sums(const void *vec, const void *pos, int64_t n, const int64_t *offsets, int32_t n_body,
+                 const void *centres, const void *dv, double dv_all, int32_t dtype, int32_t periodic,
+                 double *sum_out, double *moment_out, void *stream);
 int ot_mdf(const ot_tree *tree, void *field, const void *pos, const void *target, int32_t dtype,
            int64_t n, int32_t n_iter, double dt, double rho, int32_t mode, void *force_lag,
            void *force_eul, void *work, void *stream);

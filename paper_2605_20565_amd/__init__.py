@@ -56,7 +56,7 @@ OT_TUNE_SORT_POINTS = 1
 EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_get", "ot_tree_leaves",
            "ot_locate", "ot_interpolate", "ot_spread", "ot_track", "ot_grad_pos", "ot_batch_plan_create",
            "ot_batch_run", "ot_batch_plan_shape", "ot_batch_plan_timing", "ot_batch_last_kernel_ms",
-           "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes")
+           "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums")
 
 
 def _load():
@@ -83,6 +83,7 @@ def _load():
         "ot_batch_last_kernel_ms": [P, ctypes.POINTER(ctypes.c_float)],
         "ot_batch_plan_destroy": [P],
         "ot_mdf": [P, P, P, P, i32, i64, i32, ctypes.c_double, ctypes.c_double, i32, P, P, P, P],
+        "ot_body_sums": [P, P, i64, P, i32, P, P, ctypes.c_double, i32, i32, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -312,6 +313,35 @@ class Tree:
         _check(lib.ot_mdf(self._h, _ptr(u), _ptr(pos), _ptr(target), _dtype_code(pos), n, int(n_iter),
                           float(dt), float(rho), mcode, _ptr(f_lag), _ptr(f_eul), _ptr(work), _stream()))
         return u, f_lag, f_eul
+
+
+def body_sums(vec: torch.Tensor, pos: torch.Tensor, offsets, centres: torch.Tensor, dV=1.0,
+              periodic: bool = True) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Per-body sums (ot_body_sums): returns (S, M), FP64 (n_body, 3):
+    S_b = sum v dV and M_b = sum (X - x_b) x v dV over each body's points."""
+    pos = _rows3(pos, "pos")
+    vec = _rows3(vec, "vec")
+    centres = _rows3(centres, "centres")
+    if vec.shape[0] != pos.shape[0] or vec.dtype != pos.dtype or centres.dtype != pos.dtype:
+        raise ValueError("vec must match pos in shape and dtype; centres in dtype")
+    offs = torch.as_tensor(offsets, dtype=torch.int64, device=pos.device).contiguous()
+    nb = offs.numel() - 1
+    if nb != centres.shape[0]:
+        raise ValueError("need one centre per body (len(offsets) - 1)")
+    dv_t = None
+    dv_all = 0.0
+    if isinstance(dV, torch.Tensor):
+        dv_t = dV.to(pos.dtype).contiguous()
+        if dv_t.numel() != pos.shape[0] or dv_t.device != pos.device:
+            raise ValueError("dV must be a scalar or one value per point on the points' device")
+    else:
+        dv_all = float(dV)
+    S = torch.empty((nb, 3), dtype=torch.float64, device=pos.device)
+    M = torch.empty((nb, 3), dtype=torch.float64, device=pos.device)
+    _check(lib.ot_body_sums(_ptr(vec), _ptr(pos), pos.shape[0], _ptr(offs), nb, _ptr(centres),
+                            _ptr(dv_t) if dv_t is not None else None, dv_all, _dtype_code(pos), int(bool(periodic)),
+                            _ptr(S), _ptr(M), _stream()))
+    return S, M
 
 
 class BatchPlan:

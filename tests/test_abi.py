@@ -66,3 +66,10 @@ def test_mdf_host_side_validation(ot):
     assert L.ot_mdf_workspace_bytes(None, 10, 0) == -1
     assert L.ot_mdf(None, None, None, None, 0, 10, 3, 1.0, 1.0, 1, None, None, None, None) == -1
     assert b"tree is NULL" in L.ot_last_error()
+
+
+def test_body_sums_host_side_validation(ot):
+    L = ot.lib
+    assert L.ot_body_sums(None, None, 10, None, 2, None, None, 1.0, 0, 1, None, None, None) == -1
+    assert L.ot_body_sums(None, None, 10, None, 0, None, None, 1.0, 0, 1, None, None, None) == 0
+    assert L.ot_body_sums(None, None, -1, None, 1, None, None, 1.0, 0, 1, None, None, None) == -1
