@@ -58,6 +58,30 @@ __host__ __device__ __forceinline__ uint32_t interleave3(uint32_t x, uint32_t y,
     return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
 }
 
+// 64-bit Morton keys at 21 bits per axis (x lowest): spread the low 21 bits
+// of v so that bit b lands on bit 3b, and the inverse.
+__host__ __device__ __forceinline__ uint64_t split3_21(uint64_t v)
+{
+    v &= 0x1FFFFFull;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__host__ __device__ __forceinline__ uint32_t compact3_21(uint64_t v)
+{
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10C30C30C30C30C3ull;
+    v = (v ^ (v >> 4)) & 0x100F00F00F00F00Full;
+    v = (v ^ (v >> 8)) & 0x1F0000FF0000FFull;
+    v = (v ^ (v >> 16)) & 0x1F00000000FFFFull;
+    v = (v ^ (v >> 32)) & 0x1FFFFFull;
+    return (uint32_t)v;
+}
+
 // Table entry of the leaf containing the finest-level cell (ix, iy, iz).
 __device__ __forceinline__ uint32_t descend(const TreeView &tv, uint32_t ix, uint32_t iy,
                                             uint32_t iz)

@@ -25,28 +25,6 @@ constexpr int kSortTile = kSortThreads * kSortItems;   // 2048 keys per workgrou
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 
-__host__ __device__ __forceinline__ uint64_t split3_21(uint64_t v)
-{
-    v &= 0x1FFFFFull;
-    v = (v | (v << 32)) & 0x1F00000000FFFFull;
-    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
-    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
-    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
-    v = (v | (v << 2)) & 0x1249249249249249ull;
-    return v;
-}
-
-__host__ __device__ __forceinline__ uint32_t compact3_21(uint64_t v)
-{
-    v &= 0x1249249249249249ull;
-    v = (v ^ (v >> 2)) & 0x10C30C30C30C30C3ull;
-    v = (v ^ (v >> 4)) & 0x100F00F00F00F00Full;
-    v = (v ^ (v >> 8)) & 0x1F0000FF0000FFull;
-    v = (v ^ (v >> 16)) & 0x1F00000000FFFFull;
-    v = (v ^ (v >> 32)) & 0x1FFFFFull;
-    return (uint32_t)v;
-}
-
 __global__ void k_encode_keys(const uint32_t *__restrict__ a, int64_t n, uint64_t *__restrict__ keys)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
