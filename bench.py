@@ -341,6 +341,9 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
     # multi-direct forcing (5 iterations) on the workload's bubble markers
     res["mdf"] = mdf_measure(w, tree, field, dev, dt, args.mode, torch, timeit)
 
+    # migration phase I: relocation after a sub-cell move, owners under an 8-way leaf partition
+    res["migration"] = migration_measure(w, tree, pos, dev, torch, timeit)
+
     # launch latency on the small workload 1 (11k points; latency bound, so no roofline figure)
     res["config1_latency_us"] = config1_latency(dev, dt, args.mode, ot, torch, timeit)
 
@@ -354,6 +357,30 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
     # error against the oracle on a sample of the same inputs
     res["error_vs_oracle"] = oracle_check(w, tree, dev, dt, torch)
     return res
+
+
+def migration_measure(w, tree, pos, dev, torch, timeit, P=8):
+    n = pos.shape[0]
+    dx = 1.0 / (1 << w.tree.l_max)
+    g = torch.Generator(device=dev).manual_seed(3)
+    moved_pos = torch.remainder(pos + 0.3 * dx * torch.randn(pos.shape, generator=g, device=dev, dtype=pos.dtype), 1.0)
+    ids0 = tree.locate(pos)
+    ids = ids0.clone()
+
+    def reloc():
+        ids.copy_(ids0)
+        tree.relocate(moved_pos, ids, count=False)
+    moved = tree.relocate(moved_pos, ids0.clone())
+    reloc_ms = timeit(reloc, 10)
+    copy_ms = timeit(lambda: ids.copy_(ids0), 10)
+    out = torch.empty_like(ids0)
+    locate_ms = timeit(lambda: tree.locate(moved_pos, out=out), 10)
+    split = tree.leaf_splitters(P)
+    owner_ms = timeit(lambda: tree.find_owner(split, moved_pos), 10)
+    _, counts = tree.find_owner(split, moved_pos)
+    return {"points": n, "displacement": "0.3 dx_finest rms per axis", "moved": moved,
+            "relocate_ms": round(reloc_ms - copy_ms, 4), "full_locate_ms": round(locate_ms, 4),
+            "owners": P, "find_owner_ms": round(owner_ms, 4), "per_owner_counts": counts.cpu().tolist()}
 
 
 def mdf_measure(w, tree, field, dev, dt, mode, torch, timeit, n_iter=5):

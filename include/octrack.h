@@ -217,6 +217,31 @@ int64_t ot_mdf_workspace_bytes(const ot_tree *tree, int64_t n, int32_t dtype);
 int ot_body_sums(const void *vec, const void *pos, int64_t n, const int64_t *offsets, int32_t n_body,
                  const void *centres, const void *dv, double dv_all, int32_t dtype, int32_t periodic,
                  double *sum_out, double *moment_out, void *stream);
+
+/* Phase I of the migration of Lagrangian points (Algorithm 2), one device.
+ *
+ * ot_relocate: ids (n,) holds each point's previous host leaf id (or -1) on
+ * entry and its host after the move on exit, identical to ot_locate.  A
+ * point whose previous host still contains it keeps it (one key and level
+ * load); the others descend the table again.  moved (nullable, device
+ * int64 scalar) receives the number of points whose id changed.
+ *
+ * ot_leaf_splitters: the partition of the leaves into P contiguous Morton
+ * ranges of equal leaf count (Sec. 3.1): splitters (device int64, P + 1)
+ * with splitters[0] = 0, splitters[r] = key of leaf floor(r n_leaves / P),
+ * splitters[P] = 8^l_max.  1 <= P <= min(4096, n_leaves).
+ *
+ * ot_find_owner: owner[k] (n,) = the rank r with splitters[r] <= key <
+ * splitters[r+1], key = Morton key of the point's finest-level cell
+ * floor(x 2^l_max) (wrapped when periodic); -1 for a point with no cell.
+ * counts (nullable, device int64 (P,)) receives the number of points per
+ * rank (send-buffer sizes).  1 <= P <= 4096.  Errors: OT_ERR_INVALID,
+ * OT_ERR_LEVEL_RANGE, OT_ERR_HIP. */
+int ot_relocate(const ot_tree *tree, const void *pos, int32_t dtype, int64_t n, int32_t *ids,
+                int64_t *moved, void *stream);
+int ot_leaf_splitters(const ot_tree *tree, int32_t P, int64_t *splitters, void *stream);
+int ot_find_owner(const int64_t *splitters, int32_t P, int32_t l_max, int32_t periodic, const void *pos,
+                  int32_t dtype, int64_t n, int32_t *owner, int64_t *counts, void *stream);
 int ot_mdf(const ot_tree *tree, void *field, const void *pos, const void *target, int32_t dtype,
            int64_t n, int32_t n_iter, double dt, double rho, int32_t mode, void *force_lag,
            void *force_eul, void *work, void *stream);

@@ -56,7 +56,8 @@ OT_TUNE_SORT_POINTS = 1
 EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_get", "ot_tree_leaves",
            "ot_locate", "ot_interpolate", "ot_spread", "ot_track", "ot_grad_pos", "ot_batch_plan_create",
            "ot_batch_run", "ot_batch_plan_shape", "ot_batch_plan_timing", "ot_batch_last_kernel_ms",
-           "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums")
+           "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums",
+           "ot_relocate", "ot_leaf_splitters", "ot_find_owner")
 
 
 def _load():
@@ -84,6 +85,9 @@ def _load():
         "ot_batch_plan_destroy": [P],
         "ot_mdf": [P, P, P, P, i32, i64, i32, ctypes.c_double, ctypes.c_double, i32, P, P, P, P],
         "ot_body_sums": [P, P, i64, P, i32, P, P, ctypes.c_double, i32, i32, P, P, P],
+        "ot_relocate": [P, P, i32, i64, P, P, P],
+        "ot_leaf_splitters": [P, i32, P, P],
+        "ot_find_owner": [P, i32, i32, i32, P, i32, i64, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -289,6 +293,33 @@ class Tree:
         _check(lib.ot_grad_pos(self._h, _ptr(field), _ptr(vec), _ptr(pos), _dtype_code(pos), pos.shape[0],
                                _ptr(g), _stream()))
         return g
+
+    def relocate(self, pos: torch.Tensor, ids: torch.Tensor, count: bool = True) -> Optional[int]:
+        """Update `ids` (previous hosts, int32) in place to the hosts of the
+        moved points (ot_relocate); returns how many changed (count=False:
+        nothing, and no synchronisation)."""
+        pos = _rows3(pos, "pos")
+        if ids.dtype != torch.int32 or ids.numel() != pos.shape[0] or not ids.is_contiguous():
+            raise ValueError("ids must be a contiguous int32 tensor with one entry per point")
+        moved = torch.empty(1, dtype=torch.int64, device=pos.device) if count else None
+        _check(lib.ot_relocate(self._h, _ptr(pos), _dtype_code(pos), pos.shape[0], _ptr(ids), _ptr(moved),
+                               _stream()))
+        return int(moved.item()) if count else None
+
+    def leaf_splitters(self, P: int) -> torch.Tensor:
+        out = torch.empty(P + 1, dtype=torch.int64, device=self.device)
+        _check(lib.ot_leaf_splitters(self._h, int(P), _ptr(out), _stream()))
+        return out
+
+    def find_owner(self, splitters: torch.Tensor, pos: torch.Tensor) -> Tuple[torch.Tensor, torch.Tensor]:
+        """(owner int32 (n,), counts int64 (P,)) under the given partition."""
+        pos = _rows3(pos, "pos")
+        P = splitters.numel() - 1
+        owner = torch.empty(pos.shape[0], dtype=torch.int32, device=pos.device)
+        counts = torch.empty(P, dtype=torch.int64, device=pos.device)
+        _check(lib.ot_find_owner(_ptr(splitters.contiguous()), P, self.l_max, int(self.periodic), _ptr(pos),
+                                 _dtype_code(pos), pos.shape[0], _ptr(owner), _ptr(counts), _stream()))
+        return owner, counts
 
     def mdf(self, field: torch.Tensor, pos: torch.Tensor, target: torch.Tensor, n_iter: int, dt: float = 1.0,
             rho: float = 1.0, mode: str = "fixed", inplace: bool = False,

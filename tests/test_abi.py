@@ -73,3 +73,11 @@ def test_body_sums_host_side_validation(ot):
     assert L.ot_body_sums(None, None, 10, None, 2, None, None, 1.0, 0, 1, None, None, None) == -1
     assert L.ot_body_sums(None, None, 10, None, 0, None, None, 1.0, 0, 1, None, None, None) == 0
     assert L.ot_body_sums(None, None, -1, None, 1, None, None, 1.0, 0, 1, None, None, None) == -1
+
+
+def test_migration_host_side_validation(ot):
+    L = ot.lib
+    assert L.ot_relocate(None, None, 0, 5, None, None, None) == -1
+    assert L.ot_leaf_splitters(None, 4, None, None) == -1
+    assert L.ot_find_owner(None, 0, 5, 1, None, 0, 10, None, None, None) == -1
+    assert L.ot_find_owner(None, 4, 22, 1, None, 0, 10, None, None, None) == -4
