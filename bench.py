@@ -341,6 +341,9 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
     # multi-direct forcing (5 iterations) on the workload's bubble markers
     res["mdf"] = mdf_measure(w, tree, field, dev, dt, args.mode, torch, timeit)
 
+    # point-particle step (trilinear, drag, AB2, relocation) on the workload's particle groups
+    res["particle_step"] = particle_measure(w, tree, field, dev, dt, torch, timeit)
+
     # migration phase I: relocation after a sub-cell move, owners under an 8-way leaf partition
     res["migration"] = migration_measure(w, tree, pos, dev, torch, timeit)
 
@@ -357,6 +360,22 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
     # error against the oracle on a sample of the same inputs
     res["error_vs_oracle"] = oracle_check(w, tree, dev, dt, torch)
     return res
+
+
+def particle_measure(w, tree, field, dev, dt, torch, timeit):
+    idx = [i for i, k in enumerate(w.kinds) if k == "particles"]
+    if not idx:
+        return None
+    sel = np.concatenate([np.arange(w.instances[i], w.instances[i + 1]) for i in idx])
+    X = torch.from_numpy(np.ascontiguousarray(w.points[sel])).to(dev, dt)
+    V = torch.zeros_like(X)
+    VP = torch.zeros_like(X)
+    AP = torch.zeros_like(X)
+    ids = tree.locate(X)
+    prm = dict(dt0=1e-3, r_p=1e-3, rho_p=2.5, rho_f=1.0, nu=1e-3, g=(0.0, 0.0, -1.0))
+    tree.particle_step(field, X, V, VP, AP, ids, first=True, **prm)
+    ms = timeit(lambda: tree.particle_step(field, X, V, VP, AP, ids, **prm), 10)
+    return {"particles": int(X.shape[0]), "ms_per_step": round(ms, 4), "particles_per_s": X.shape[0] / (ms * 1e-3)}
 
 
 def migration_measure(w, tree, pos, dev, torch, timeit, P=8):

@@ -242,6 +242,36 @@ int ot_relocate(const ot_tree *tree, const void *pos, int32_t dtype, int64_t n, 
 int ot_leaf_splitters(const ot_tree *tree, int32_t P, int64_t *splitters, void *stream);
 int ot_find_owner(const int64_t *splitters, int32_t P, int32_t l_max, int32_t periodic, const void *pos,
                   int32_t dtype, int64_t n, int32_t *owner, int64_t *counts, void *stream);
+
+/* Parameters of the point-particle step (physical units). */
+typedef struct {
+    double dt0;      /* time step at level l_min; level l uses dt0 / 2^(l - l_min)  */
+    double r_p;      /* particle radius                                              */
+    double rho_p;    /* particle density                                             */
+    double rho_f;    /* fluid density                                                */
+    double nu;       /* kinematic viscosity                                          */
+    double g[3];     /* gravitational acceleration                                   */
+    int32_t first;   /* 1: forward Euler (no history yet), 0: Adams-Bashforth 2      */
+    int32_t reserved;
+} ot_particle_params;
+
+/* One step of point-like particles (Sec. 2.3): host leaf, fluid velocity u
+ * by trilinear interpolation at the host level (the 8 level-l cells around
+ * x 2^l - 1/2, each read from the leaf containing its centre; periodic wrap,
+ * nodes beyond walls dropped), Re = 2 r_p |u - v| / nu,
+ * a = (1 + 0.15 Re^0.687)(u - v) / tau + (1 - rho_f / rho_p) g with
+ * tau = 2 rho_p r_p^2 / (9 rho_f nu), then
+ *   v <- v + dt_l (3/2 a - 1/2 acc_prev),  x <- x + dt_l (3/2 v - 1/2 vel_prev)
+ * (forward Euler when params->first), x wrapped into the periodic cube, and
+ * ids <- host after the move.  vel_prev and acc_prev receive this step's v
+ * and a.  A particle with no host does not move.  All arrays (n, 3) dtype
+ * except ids (n,) int32, updated in place; field (n_leaves, 3).  Physical
+ * units: the previous acceleration needs no rescale when the host level
+ * changes (the paper's lattice-unit rescale is that unit change).
+ * Errors: OT_ERR_INVALID, OT_ERR_HIP. */
+int ot_particle_step(const ot_tree *tree, const void *field, void *pos, void *vel, void *vel_prev,
+                     void *acc_prev, int32_t *ids, int32_t dtype, int64_t n,
+                     const ot_particle_params *params, void *stream);
 int ot_mdf(const ot_tree *tree, void *field, const void *pos, const void *target, int32_t dtype,
            int64_t n, int32_t n_iter, double dt, double rho, int32_t mode, void *force_lag,
            void *force_eul, void *work, void *stream);

@@ -45,6 +45,12 @@ class TreeInfo(ctypes.Structure):
                 ("table_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
+class ParticleParams(ctypes.Structure):
+    _fields_ = [("dt0", ctypes.c_double), ("r_p", ctypes.c_double), ("rho_p", ctypes.c_double),
+                ("rho_f", ctypes.c_double), ("nu", ctypes.c_double), ("g", ctypes.c_double * 3),
+                ("first", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("flags", ctypes.c_int32)]
@@ -57,7 +63,7 @@ EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_g
            "ot_locate", "ot_interpolate", "ot_spread", "ot_track", "ot_grad_pos", "ot_batch_plan_create",
            "ot_batch_run", "ot_batch_plan_shape", "ot_batch_plan_timing", "ot_batch_last_kernel_ms",
            "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums",
-           "ot_relocate", "ot_leaf_splitters", "ot_find_owner")
+           "ot_relocate", "ot_leaf_splitters", "ot_find_owner", "ot_particle_step")
 
 
 def _load():
@@ -88,6 +94,7 @@ def _load():
         "ot_relocate": [P, P, i32, i64, P, P, P],
         "ot_leaf_splitters": [P, i32, P, P],
         "ot_find_owner": [P, i32, i32, i32, P, i32, i64, P, P, P],
+        "ot_particle_step": [P, P, P, P, P, P, P, i32, i64, ctypes.POINTER(ParticleParams), P],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -320,6 +327,24 @@ class Tree:
         _check(lib.ot_find_owner(_ptr(splitters.contiguous()), P, self.l_max, int(self.periodic), _ptr(pos),
                                  _dtype_code(pos), pos.shape[0], _ptr(owner), _ptr(counts), _stream()))
         return owner, counts
+
+    def particle_step(self, field: torch.Tensor, pos: torch.Tensor, vel: torch.Tensor, vel_prev: torch.Tensor,
+                      acc_prev: torch.Tensor, ids: torch.Tensor, dt0: float, r_p: float, rho_p: float, rho_f: float,
+                      nu: float, g=(0.0, 0.0, 0.0), first: bool = False) -> None:
+        """One point-particle step (ot_particle_step), all state in place."""
+        pos = _rows3(pos, "pos")
+        for name, tns in (("vel", vel), ("vel_prev", vel_prev), ("acc_prev", acc_prev)):
+            if tns.shape != pos.shape or tns.dtype != pos.dtype or not tns.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous (n, 3) tensor of the dtype of pos")
+        field = _rows3(field, "field")
+        if field.shape[0] != self.n_leaves or field.dtype != pos.dtype:
+            raise ValueError("field must be (n_leaves, 3) with the dtype of pos")
+        if ids.dtype != torch.int32 or ids.numel() != pos.shape[0] or not ids.is_contiguous():
+            raise ValueError("ids must be a contiguous int32 tensor with one entry per point")
+        prm = ParticleParams(float(dt0), float(r_p), float(rho_p), float(rho_f), float(nu),
+                             (ctypes.c_double * 3)(*[float(x) for x in g]), int(bool(first)), 0)
+        _check(lib.ot_particle_step(self._h, _ptr(field), _ptr(pos), _ptr(vel), _ptr(vel_prev), _ptr(acc_prev),
+                                    _ptr(ids), _dtype_code(pos), pos.shape[0], ctypes.byref(prm), _stream()))
 
     def mdf(self, field: torch.Tensor, pos: torch.Tensor, target: torch.Tensor, n_iter: int, dt: float = 1.0,
             rho: float = 1.0, mode: str = "fixed", inplace: bool = False,

@@ -1,0 +1,135 @@
+// Point-particle step (Sec. 2.3, point-like particles), one thread per
+// particle: host leaf, fluid velocity by trilinear interpolation at the host
+// level (8 nodes, each read from the leaf containing the node's centre),
+// Schiller-Naumann drag and buoyancy, second-order Adams-Bashforth with the
+// host level's time step dt0 / 2^(l - l_min), and the host after the move.
+// Physical units throughout: the paper's rescale of the previous acceleration
+// when a particle changes level (a_c = 2 a_f in lattice units) is the unit
+// change itself, so the previous acceleration carries over unchanged.
+#include <hip/hip_runtime.h>
+
+#include "ot_common.h"
+
+namespace ot {
+namespace {
+
+template <typename T, bool PER>
+__global__ __launch_bounds__(256) void k_particle_step(TreeView tv, int l_min, int64_t n, const T *__restrict__ field,
+                                                       T *__restrict__ pos, T *__restrict__ vel,
+                                                       T *__restrict__ vel_prev, T *__restrict__ acc_prev,
+                                                       int32_t *__restrict__ ids, ot_particle_params p)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const T X[3] = {pos[3 * k], pos[3 * k + 1], pos[3 * k + 2]};
+    const T V[3] = {vel[3 * k], vel[3 * k + 1], vel[3 * k + 2]};
+    const T Vp[3] = {vel_prev[3 * k], vel_prev[3 * k + 1], vel_prev[3 * k + 2]};
+    const T Ap[3] = {acc_prev[3 * k], acc_prev[3 * k + 1], acc_prev[3 * k + 2]};
+    uint32_t I[3];
+    const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
+    T U[3] = {T(0), T(0), T(0)};
+    double dt = 0.0;
+    if (ok) {
+        const uint32_t e = descend(tv, I[0], I[1], I[2]);
+        const int l = (int)((e >> kLevelShift) & 31u);
+        const int sh = tv.L - l;
+        const int64_t M = int64_t(1) << l;
+        const uint32_t half = sh > 0 ? (1u << (sh - 1)) : 0u;
+        int64_t i0[3];
+        T t[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double s = (double)X[d] * (double)M - 0.5;
+            const double f = floor(s);
+            i0[d] = (int64_t)f;
+            t[d] = (T)(s - f);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int o[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
+            uint32_t nc[3];
+            bool in = true;
+            T w = T(1);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                int64_t c = i0[d] + o[d];
+                if (PER) c &= (M - 1);
+                else in = in && c >= 0 && c < M;
+                nc[d] = (uint32_t)(((c < 0 ? 0 : c) << sh) | half);
+                w *= o[d] ? t[d] : T(1) - t[d];
+            }
+            if (!in) continue;   // node outside the walls: dropped with its weight
+            const int64_t j = 3 * (int64_t)(descend(tv, nc[0], nc[1], nc[2]) & kIdMask);
+            U[0] = fma(w, field[j], U[0]);
+            U[1] = fma(w, field[j + 1], U[1]);
+            U[2] = fma(w, field[j + 2], U[2]);
+        }
+        dt = ldexp(p.dt0, -(l - l_min));
+    }
+    // drag (Schiller-Naumann) and buoyancy
+    const T rel[3] = {U[0] - V[0], U[1] - V[1], U[2] - V[2]};
+    const T mag = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
+    const T re = (T)(2.0 * p.r_p / p.nu) * mag;
+    const T fd = T(1) + T(0.15) * pow(re, T(0.687));
+    const T inv_tau = (T)(9.0 * p.rho_f * p.nu / (2.0 * p.rho_p * p.r_p * p.r_p));
+    const T buoy = (T)(1.0 - p.rho_f / p.rho_p);
+    T A[3], Vn[3], Xn[3];
+    const T h = (T)dt;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        A[d] = fd * rel[d] * inv_tau + buoy * (T)p.g[d];
+        if (p.first) {
+            Vn[d] = V[d] + h * A[d];
+            Xn[d] = X[d] + h * V[d];
+        } else {
+            Vn[d] = V[d] + h * (T(1.5) * A[d] - T(0.5) * Ap[d]);
+            Xn[d] = X[d] + h * (T(1.5) * V[d] - T(0.5) * Vp[d]);
+        }
+        if (PER) Xn[d] = Xn[d] - floor(Xn[d]);
+    }
+    uint32_t In[3];
+    const bool okn = point_cell<T>(tv, Xn[0], Xn[1], Xn[2], In);
+    ids[k] = okn ? (int32_t)(descend(tv, In[0], In[1], In[2]) & kIdMask) : -1;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        pos[3 * k + d] = Xn[d];
+        vel[3 * k + d] = Vn[d];
+        vel_prev[3 * k + d] = V[d];
+        acc_prev[3 * k + d] = A[d];
+    }
+}
+
+}  // namespace
+}  // namespace ot
+
+using namespace ot;
+
+extern "C" int ot_particle_step(const ot_tree *t, const void *field, void *pos, void *vel, void *vel_prev,
+                                void *acc_prev, int32_t *ids, int32_t dtype, int64_t n,
+                                const ot_particle_params *params, void *stream)
+{
+    if (!t || !params) return fail(OT_ERR_INVALID, "ot_particle_step: tree or params is NULL");
+    if (dtype != OT_F32 && dtype != OT_F64) return fail(OT_ERR_INVALID, "dtype must be OT_F32 or OT_F64");
+    if (n < 0) return fail(OT_ERR_INVALID, "n < 0");
+    if (n > 0 && (!field || !pos || !vel || !vel_prev || !acc_prev || !ids))
+        return fail(OT_ERR_INVALID, "ot_particle_step: NULL array");
+    const ot_particle_params &p = *params;
+    if (!(p.dt0 >= 0.0) || !(p.r_p > 0.0) || !(p.rho_p > 0.0) || !(p.rho_f >= 0.0) || !(p.nu > 0.0))
+        return fail(OT_ERR_INVALID, "ot_particle_step: need dt0 >= 0, r_p, rho_p, nu > 0, rho_f >= 0");
+    if (n == 0) return OT_OK;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    hipStream_t s = (hipStream_t)stream;
+#define OT_PSTEP(TT, PERV)                                                                                      \
+    hipLaunchKernelGGL((k_particle_step<TT, PERV>), g, b, 0, s, t->view, (int)t->l_min, n, (const TT *)field, \
+                       (TT *)pos, (TT *)vel, (TT *)vel_prev, (TT *)acc_prev, ids, p)
+    if (dtype == OT_F32) {
+        if (t->view.periodic) OT_PSTEP(float, true);
+        else OT_PSTEP(float, false);
+    } else {
+        if (t->view.periodic) OT_PSTEP(double, true);
+        else OT_PSTEP(double, false);
+    }
+#undef OT_PSTEP
+    OT_HIP(hipGetLastError());
+    return OT_OK;
+}

@@ -81,3 +81,8 @@ def test_migration_host_side_validation(ot):
     assert L.ot_leaf_splitters(None, 4, None, None) == -1
     assert L.ot_find_owner(None, 0, 5, 1, None, 0, 10, None, None, None) == -1
     assert L.ot_find_owner(None, 4, 22, 1, None, 0, 10, None, None, None) == -4
+
+
+def test_particle_step_host_side_validation(ot):
+    L = ot.lib
+    assert L.ot_particle_step(None, None, None, None, None, None, None, 0, 1, None, None) == -1
