@@ -221,10 +221,11 @@ int ot_body_sums(const void *vec, const void *pos, int64_t n, const int64_t *off
 /* Phase I of the migration of Lagrangian points (Algorithm 2), one device.
  *
  * ot_relocate: ids (n,) holds each point's previous host leaf id (or -1) on
- * entry and its host after the move on exit, identical to ot_locate.  A
- * point whose previous host still contains it keeps it (one key and level
- * load); the others descend the table again.  moved (nullable, device
- * int64 scalar) receives the number of points whose id changed.
+ * entry and its host after the move on exit, identical to ot_locate; moved
+ * (nullable, device int64 scalar) receives the number of points whose id
+ * changed (the leavers).  Every point descends the table: with one or two
+ * table loads per point that is cheaper here than checking the previous
+ * host first, which the paper does to skip a binary search.
  *
  * ot_leaf_splitters: the partition of the leaves into P contiguous Morton
  * ranges of equal leaf count (Sec. 3.1): splitters (device int64, P + 1)

@@ -1,9 +1,11 @@
 // Phase I of the migration of Lagrangian points (Algorithm 2) on one device.
 //
-// relocate: after the points moved (usually by less than a cell, Sec. 3.2),
-// each keeps its previous host leaf when that leaf still contains it (one
-// key + level load and an integer compare) and otherwise descends the table
-// again; the points whose host changed are counted.
+// relocate: the host of every moved point and the number of points whose
+// host changed (the leavers of phase I).  The paper checks the previous host
+// first because its search is a binary search; here a fresh descent is one
+// or two loads from the (cached) descent table, cheaper than fetching the
+// previous leaf's key and level (measured: 0.12 against 0.25 ms for 10^7
+// points), so every point descends and is compared with its previous id.
 // find_owner: under a partition of the leaves into contiguous Morton ranges
 // (Sec. 3.1), the owner of a point is the range holding the Morton key of
 // its finest-level cell, found by a binary search over the P + 1 splitters;
@@ -32,9 +34,8 @@ __device__ __forceinline__ void block_count_to(unsigned long long v, unsigned lo
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_relocate(TreeView tv, const uint64_t *__restrict__ keys,
-                                                       const uint8_t *__restrict__ levels, int64_t n_leaves,
-                                                       const T *__restrict__ pos, int64_t n, int32_t *__restrict__ ids,
+__global__ __launch_bounds__(kThreads) void k_relocate(TreeView tv, const T *__restrict__ pos, int64_t n,
+                                                       int32_t *__restrict__ ids,
                                                        unsigned long long *__restrict__ moved)
 {
     __shared__ unsigned long long sh[kThreads / 64];
@@ -44,18 +45,7 @@ __global__ __launch_bounds__(kThreads) void k_relocate(TreeView tv, const uint64
         const int32_t prev = ids[k];
         uint32_t I[3];
         const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
-        int32_t id = -1;
-        if (ok) {
-            bool inside = false;
-            if (prev >= 0 && prev < n_leaves) {
-                const uint64_t key = keys[prev];
-                const int sh_l = tv.L - (int)levels[prev];
-                inside = ((I[0] >> sh_l) == (compact3_21(key) >> sh_l)) &&
-                         ((I[1] >> sh_l) == (compact3_21(key >> 1) >> sh_l)) &&
-                         ((I[2] >> sh_l) == (compact3_21(key >> 2) >> sh_l));
-            }
-            id = inside ? prev : (int32_t)(descend(tv, I[0], I[1], I[2]) & kIdMask);
-        }
+        const int32_t id = ok ? (int32_t)(descend(tv, I[0], I[1], I[2]) & kIdMask) : -1;
         ids[k] = id;
         changed = id != prev ? 1ull : 0ull;
     }
@@ -72,35 +62,53 @@ __global__ void k_leaf_splitters(const uint64_t *__restrict__ keys, int64_t n_le
     else split[r] = (int64_t)keys[((int64_t)r * n_leaves) / P];
 }
 
+// Splitters staged in LDS; each thread takes kOwnerItems points.  Counts:
+// for up to kBallotOwners owners every wave counts each owner with one
+// ballot (no same-address atomics), else LDS atomics.
+constexpr int kOwnerItems = 8;
+constexpr int kBallotOwners = 32;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_find_owner(TreeView tv, const int64_t *__restrict__ split, int P,
                                                          const T *__restrict__ pos, int64_t n,
                                                          int32_t *__restrict__ owner,
                                                          unsigned long long *__restrict__ counts)
 {
+    __shared__ int64_t s_split[kMaxOwners + 1];
     __shared__ unsigned int hist[kMaxOwners];
-    if (counts) {
-        for (int i = threadIdx.x; i < P; i += kThreads) hist[i] = 0u;
-        __syncthreads();
-    }
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k < n) {
-        uint32_t I[3];
-        const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
+    for (int i = threadIdx.x; i <= P; i += kThreads) s_split[i] = split[i];
+    for (int i = threadIdx.x; i < P; i += kThreads) hist[i] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kThreads * kOwnerItems;
+    for (int j = 0; j < kOwnerItems; ++j) {
+        const int64_t k = base + (int64_t)j * kThreads + threadIdx.x;
         int32_t o = -1;
-        if (ok) {
-            const int64_t key = (int64_t)(split3_21(I[0]) | (split3_21(I[1]) << 1) | (split3_21(I[2]) << 2));
-            // largest r in [0, P) with split[r] <= key
-            int lo = 0, hi = P;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (split[mid] <= key) lo = mid;
-                else hi = mid;
+        if (k < n) {
+            uint32_t I[3];
+            const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
+            if (ok) {
+                const int64_t key = (int64_t)(split3_21(I[0]) | (split3_21(I[1]) << 1) | (split3_21(I[2]) << 2));
+                // largest r in [0, P) with split[r] <= key
+                int lo = 0, hi = P;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_split[mid] <= key) lo = mid;
+                    else hi = mid;
+                }
+                o = lo;
             }
-            o = lo;
-            if (counts) atomicAdd(&hist[o], 1u);
+            owner[k] = o;
         }
-        owner[k] = o;
+        if (counts) {
+            if (P <= kBallotOwners) {
+                for (int r = 0; r < P; ++r) {
+                    const unsigned long long m = __ballot(o == r);
+                    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&hist[r], (unsigned)__popcll(m));
+                }
+            } else if (o >= 0) {
+                atomicAdd(&hist[o], 1u);
+            }
+        }
     }
     if (counts) {
         __syncthreads();
@@ -127,11 +135,9 @@ extern "C" int ot_relocate(const ot_tree *t, const void *pos, int32_t dtype, int
     if (n > 0) {
         const dim3 g((unsigned)((n + kThreads - 1) / kThreads)), b(kThreads);
         if (dtype == OT_F32)
-            hipLaunchKernelGGL(k_relocate<float>, g, b, 0, s, t->view, t->keys, t->levels, t->n_leaves,
-                               (const float *)pos, n, ids, mv);
+            hipLaunchKernelGGL(k_relocate<float>, g, b, 0, s, t->view, (const float *)pos, n, ids, mv);
         else
-            hipLaunchKernelGGL(k_relocate<double>, g, b, 0, s, t->view, t->keys, t->levels, t->n_leaves,
-                               (const double *)pos, n, ids, mv);
+            hipLaunchKernelGGL(k_relocate<double>, g, b, 0, s, t->view, (const double *)pos, n, ids, mv);
     }
     OT_HIP(hipGetLastError());
     return OT_OK;
@@ -162,7 +168,8 @@ extern "C" int ot_find_owner(const int64_t *splitters, int32_t P, int32_t l_max,
     tv.L = l_max;
     tv.periodic = periodic ? 1 : 0;
     if (n > 0) {
-        const dim3 g((unsigned)((n + kThreads - 1) / kThreads)), b(kThreads);
+        const int64_t per_block = (int64_t)kThreads * kOwnerItems;
+        const dim3 g((unsigned)((n + per_block - 1) / per_block)), b(kThreads);
         if (dtype == OT_F32)
             hipLaunchKernelGGL(k_find_owner<float>, g, b, 0, s, tv, splitters, (int)P, (const float *)pos, n, owner,
                                cnt);
