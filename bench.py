@@ -353,6 +353,9 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
     # migration phase I: relocation after a sub-cell move, owners under an 8-way leaf partition
     res["migration"] = migration_measure(w, tree, pos, dev, torch, timeit)
 
+    # differentiable pair on 10^6 markers over the workload's bubbles (workload 5's shape)
+    res["backward_1e6_markers"] = backward_measure(w, tree, field, dev, dt, args.mode, ot, torch, timeit)
+
     # launch latency on the small workload 1 (11k points; latency bound, so no roofline figure)
     res["config1_latency_us"] = config1_latency(dev, dt, args.mode, ot, torch, timeit)
 
@@ -382,6 +385,44 @@ def particle_measure(w, tree, field, dev, dt, torch, timeit):
     tree.particle_step(field, X, V, VP, AP, ids, first=True, **prm)
     ms = timeit(lambda: tree.particle_step(field, X, V, VP, AP, ids, **prm), 10)
     return {"particles": int(X.shape[0]), "ms_per_step": round(ms, 4), "particles_per_s": X.shape[0] / (ms * 1e-3)}
+
+
+def backward_measure(w, tree, field, dev, dt, mode, ot, torch, timeit, per_body=125_000):
+    """Interpolation of the leaf field at 10^6 markers (125k per bubble) and its backward: the field's
+    gradient is the spread of the upstream gradient, the markers' the phi' contraction."""
+    import synth
+    if not w.spheres:
+        return None
+    X = torch.from_numpy(np.concatenate([synth.fibonacci_sphere(s, per_body) for s in w.spheres])).to(dev, dt)
+    g = torch.randn(X.shape, generator=torch.Generator(device=dev).manual_seed(5), device=dev, dtype=dt)
+    n = X.shape[0]
+    U = torch.empty_like(X)
+    gf = torch.empty_like(field)
+    gx = torch.empty_like(X)
+    fwd = timeit(lambda: tree.interpolate(field, X, out=U), 20)
+    bwd = timeit(lambda: tree.interp_backward(field, g, X, mode=mode, grad_field=gf, grad_pos=gx), 20)
+    spr = timeit(lambda: tree.spread(g, X, mode=mode, out=gf), 20)
+    gpo = timeit(lambda: tree.grad_pos(field, g, X, out=gx), 20)
+    Xr = X.clone().requires_grad_(True)
+    ur = field.clone().requires_grad_(True)
+
+    def autograd_step():
+        (ot.interpolate(tree, ur, Xr, mode=mode) * g).sum().backward()
+        Xr.grad = None
+        ur.grad = None
+    full = timeit(autograd_step, 10)
+    touched = int((gf != 0).any(dim=1).sum())
+    b = dt.itemsize
+    per_marker = 5 * 3 * b + 2 * 4   # forward pos, id, U; backward g, pos, id, grad_X
+    per_leaf = 3 * 3 * b + 9         # field forward and backward, grad_field, key and level
+    alg = n * per_marker + touched * per_leaf
+    t_kernels = fwd + bwd
+    return {"markers": n, "touched_leaves": touched, "spread_mode": mode, "forward_ms": round(fwd, 4),
+            "backward_one_pass_ms": round(bwd, 4), "backward_separate_spread_ms": round(spr, 4),
+            "backward_separate_grad_pos_ms": round(gpo, 4), "autograd_fwd_bwd_ms": round(full, 4),
+            "markers_per_s_fwd_bwd": n / (t_kernels * 1e-3),
+            "algorithmic_GBps": round(alg / (t_kernels * 1e-3) / 1e9, 1),
+            "algorithmic_bytes": {"per_marker": per_marker, "per_touched_leaf": per_leaf}}
 
 
 def migration_measure(w, tree, pos, dev, torch, timeit, P=8):

@@ -185,6 +185,29 @@ int ot_track(const ot_tree *tree, int32_t ops, const void *field, const void *fo
 int ot_grad_pos(const ot_tree *tree, const void *field, const void *vec, const void *pos,
                 int32_t dtype, int64_t n, void *grad, void *stream);
 
+/* Backward of ot_interpolate in one pass over the points (the adjoint pair
+ * of Sec. 2.2: spreading is the transpose of interpolation), sharing the
+ * host search and the 27 node lookups:
+ *   grad_field (+)= spread(grad_vel)            (as ot_spread, mode/accumulate)
+ *   grad_pos    = ot_grad_pos(field, grad_vel)   (host leaf held fixed).
+ * field: (n_leaves, 3) forward field; grad_vel: (n, 3) dLoss/dvel.  Either
+ * output may be NULL (not computed), not both.  grad_field: (n_leaves, 3);
+ * grad_pos: (n, 3).  Uses the tree's workspace in FIXED mode, like
+ * ot_spread.  Errors: OT_ERR_INVALID for NULL inputs that an output needs,
+ * a bad mode or dtype, n < 0. */
+int ot_interp_backward(const ot_tree *tree, const void *field, const void *grad_vel, const void *pos,
+                       int32_t dtype, int64_t n, int32_t mode, int32_t accumulate, void *grad_field,
+                       void *grad_pos, void *stream);
+
+/* Backward of ot_spread in one pass over the points:
+ *   grad_force = interpolate(grad_field)          (as ot_interpolate)
+ *   grad_pos   = ot_grad_pos(grad_field, force)   (host leaf held fixed).
+ * grad_field: (n_leaves, 3) dLoss/dfield_out; force: (n, 3) forward forces.
+ * Either output may be NULL, not both; both are (n, 3) and overwritten.
+ * Errors as ot_interp_backward. */
+int ot_spread_backward(const ot_tree *tree, const void *grad_field, const void *force, const void *pos,
+                       int32_t dtype, int64_t n, void *grad_force, void *grad_pos, void *stream);
+
 /* Multi-direct forcing of the immersed-boundary method (IBM subsection of
  * Sec. 2.2), n_iter iterations of:
  *   u_k = interpolate(field) at the markers pos,

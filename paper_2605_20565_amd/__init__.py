@@ -63,7 +63,8 @@ EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_g
            "ot_locate", "ot_interpolate", "ot_spread", "ot_track", "ot_grad_pos", "ot_batch_plan_create",
            "ot_batch_run", "ot_batch_plan_shape", "ot_batch_plan_timing", "ot_batch_last_kernel_ms",
            "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums",
-           "ot_relocate", "ot_leaf_splitters", "ot_find_owner", "ot_particle_step")
+           "ot_relocate", "ot_leaf_splitters", "ot_find_owner", "ot_particle_step", "ot_interp_backward",
+           "ot_spread_backward")
 
 
 def _load():
@@ -83,6 +84,8 @@ def _load():
         "ot_spread": [P, P, P, i32, i64, i32, i32, P, P],
         "ot_track": [P, i32, P, P, P, i32, i64, i32, i32, P, P, P, P],
         "ot_grad_pos": [P, P, P, P, i32, i64, P, P],
+        "ot_interp_backward": [P, P, P, P, i32, i64, i32, i32, P, P, P],
+        "ot_spread_backward": [P, P, P, P, i32, i64, P, P, P],
         "ot_batch_plan_create": [P, P, P, i32, i32, i32, ctypes.POINTER(Tuning), ctypes.POINTER(P)],
         "ot_batch_run": [P, P, P, P, P, P, P, P],
         "ot_batch_plan_shape": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
@@ -300,6 +303,52 @@ class Tree:
         _check(lib.ot_grad_pos(self._h, _ptr(field), _ptr(vec), _ptr(pos), _dtype_code(pos), pos.shape[0],
                                _ptr(g), _stream()))
         return g
+
+    def interp_backward(self, field: torch.Tensor, grad_vel: torch.Tensor, pos: torch.Tensor, mode="atomic",
+                        need_field: bool = True, need_pos: bool = True, accumulate: bool = False,
+                        grad_field: Optional[torch.Tensor] = None, grad_pos: Optional[torch.Tensor] = None):
+        """Backward of `interpolate` in one pass: (spread(grad_vel), grad_pos(field, grad_vel)); an output
+        not asked for is None."""
+        pos = _rows3(pos, "pos")
+        field = _rows3(field, "field")
+        grad_vel = _rows3(grad_vel, "grad_vel")
+        if field.shape[0] != self.n_leaves or grad_vel.shape[0] != pos.shape[0]:
+            raise ValueError("field must be (n_leaves, 3) and grad_vel (n, 3)")
+        if field.dtype != pos.dtype or grad_vel.dtype != pos.dtype:
+            raise ValueError("field, grad_vel and pos must share a dtype")
+        if not (need_field or need_pos):
+            raise ValueError("nothing to compute")
+        gf = gx = None
+        if need_field:
+            _check_out(grad_field, self.n_leaves, pos.dtype, pos.device, "grad_field")
+            gf = grad_field if grad_field is not None else torch.empty((self.n_leaves, 3), dtype=pos.dtype,
+                                                                       device=pos.device)
+        if need_pos:
+            _check_out(grad_pos, pos.shape[0], pos.dtype, pos.device, "grad_pos")
+            gx = grad_pos if grad_pos is not None else torch.empty_like(pos)
+        _check(lib.ot_interp_backward(self._h, _ptr(field), _ptr(grad_vel), _ptr(pos), _dtype_code(pos),
+                                      pos.shape[0], _mode_code(mode), 1 if accumulate else 0, _ptr(gf), _ptr(gx),
+                                      _stream()))
+        return gf, gx
+
+    def spread_backward(self, grad_field: torch.Tensor, force: torch.Tensor, pos: torch.Tensor,
+                        need_force: bool = True, need_pos: bool = True):
+        """Backward of `spread` in one pass: (interpolate(grad_field), grad_pos(grad_field, force)); an output
+        not asked for is None."""
+        pos = _rows3(pos, "pos")
+        grad_field = _rows3(grad_field, "grad_field")
+        force = _rows3(force, "force")
+        if grad_field.shape[0] != self.n_leaves or force.shape[0] != pos.shape[0]:
+            raise ValueError("grad_field must be (n_leaves, 3) and force (n, 3)")
+        if grad_field.dtype != pos.dtype or force.dtype != pos.dtype:
+            raise ValueError("grad_field, force and pos must share a dtype")
+        if not (need_force or need_pos):
+            raise ValueError("nothing to compute")
+        gF = torch.empty_like(pos) if need_force else None
+        gx = torch.empty_like(pos) if need_pos else None
+        _check(lib.ot_spread_backward(self._h, _ptr(grad_field), _ptr(force), _ptr(pos), _dtype_code(pos),
+                                      pos.shape[0], _ptr(gF), _ptr(gx), _stream()))
+        return gF, gx
 
     def relocate(self, pos: torch.Tensor, ids: torch.Tensor, count: bool = True) -> Optional[int]:
         """Update `ids` (previous hosts, int32) in place to the hosts of the

@@ -5,7 +5,9 @@ w_kn = phi(r_x) phi(r_y) phi(r_z) (Sec. 2.2), so each is the other's adjoint:
 the backward of interpolate with respect to the leaf field is spread of the
 upstream gradient, and the backward of spread with respect to the forces is
 interpolate.  Gradients with respect to the point positions go through the
-derivative of phi (ot_grad_pos), the host leaf held fixed.
+derivative of phi, the host leaf held fixed.  Each backward is one pass over
+the points that computes both gradients (ot_interp_backward,
+ot_spread_backward).
 """
 from __future__ import annotations
 
@@ -22,9 +24,11 @@ class InterpolateFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         field, pos = ctx.saved_tensors
-        g = g.contiguous()
-        gf = ctx.tree.spread(g, pos, mode=ctx.mode) if ctx.needs_input_grad[0] else None
-        gx = ctx.tree.grad_pos(field, g, pos) if ctx.needs_input_grad[1] else None
+        need_f, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_f or need_x):
+            return None, None, None, None
+        gf, gx = ctx.tree.interp_backward(field, g.contiguous(), pos, mode=ctx.mode, need_field=need_f,
+                                          need_pos=need_x)
         return gf, gx, None, None
 
 
@@ -38,9 +42,10 @@ class SpreadFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         force, pos = ctx.saved_tensors
-        g = g.contiguous()
-        gF = ctx.tree.interpolate(g, pos) if ctx.needs_input_grad[0] else None
-        gx = ctx.tree.grad_pos(g, force, pos) if ctx.needs_input_grad[1] else None
+        need_F, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        if not (need_F or need_x):
+            return None, None, None, None
+        gF, gx = ctx.tree.spread_backward(g.contiguous(), force, pos, need_force=need_F, need_pos=need_x)
         return gF, gx, None, None
 
 

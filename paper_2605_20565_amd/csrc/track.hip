@@ -23,7 +23,7 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
                                                const T *__restrict__ field, const T *__restrict__ force,
                                                int32_t *__restrict__ ids, T *__restrict__ vel,
                                                T *__restrict__ fout, unsigned long long *__restrict__ facc,
-                                               const FxState *__restrict__ fx)
+                                               const FxState *__restrict__ fx, T *__restrict__ grad)
 {
     const int64_t start = (int64_t)blockIdx.x * tile;
     const int64_t end = start + tile < n ? start + tile : n;
@@ -36,40 +36,30 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
         LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
         sink.clear();
         __syncthreads();
-        track_range<T, OPS, PER>(tv, start, end, nullptr, 3, pos, field, force, ids, vel, sink);
+        track_range<T, OPS, PER>(tv, start, end, nullptr, 3, pos, field, force, ids, vel, sink, grad);
         sink.flush();
     } else {
         DirectSink<T, MODE> sink{fout, facc, 0.0};
-        track_range<T, OPS, PER>(tv, start, end, nullptr, 3, pos, field, force, ids, vel, sink);
+        track_range<T, OPS, PER>(tv, start, end, nullptr, 3, pos, field, force, ids, vel, sink, grad);
     }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_grad(TreeView tv, int64_t n, const T *__restrict__ pos,
-                                              const T *__restrict__ field, const T *__restrict__ vec,
-                                              T *__restrict__ grad)
-{
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    grad_point<T>(tv, k, pos, field, vec, grad);
 }
 
 constexpr int kMaxPointsPerThread = 4;
 
 template <typename T, int MODE>
 int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStream_t s, int64_t n, const void *pos,
-                 const void *field, const void *force, int32_t *ids, void *vel, void *fout)
+                 const void *field, const void *force, int32_t *ids, void *vel, void *fout, void *grad)
 {
     const T *P = (const T *)pos, *Fd = (const T *)field, *Fo = (const T *)force;
-    T *V = (T *)vel, *O = (T *)fout;
+    T *V = (T *)vel, *O = (T *)fout, *Gr = (T *)grad;
     const FxState *fx = (const FxState *)t->scratch;
 #define OT_LAUNCH(OPSV)                                                                                         \
     if (t->view.periodic)                                                                                        \
         hipLaunchKernelGGL((k_track<T, OPSV, MODE, true>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,    \
-                           t->fx_acc, fx);                                                                       \
+                           t->fx_acc, fx, Gr);                                                                   \
     else                                                                                                         \
         hipLaunchKernelGGL((k_track<T, OPSV, MODE, false>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,   \
-                           t->fx_acc, fx);                                                                       \
+                           t->fx_acc, fx, Gr);                                                                   \
     break;
     switch (ops) {
     case 1: OT_LAUNCH(1)
@@ -79,6 +69,11 @@ int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStr
     case 5: OT_LAUNCH(5)
     case 6: OT_LAUNCH(6)
     case 7: OT_LAUNCH(7)
+    // gradient passes: alone, with the interpolation (backward of spreading)
+    // or with the spreading (backward of interpolation)
+    case kOpGrad: OT_LAUNCH(kOpGrad)
+    case kOpGrad | kOpInterp: OT_LAUNCH(kOpGrad | kOpInterp)
+    case kOpGrad | kOpSpread: OT_LAUNCH(kOpGrad | kOpSpread)
     default: return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
     }
 #undef OT_LAUNCH
@@ -155,14 +150,22 @@ int check_common(const ot_tree *t, int dtype, int64_t n, const void *pos)
     return OT_OK;
 }
 
-int track(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
-          int mode, int accumulate, int32_t *ids, void *vel, void *fout, hipStream_t s)
+namespace {
+
+// One pass over the points with the ops in `ops` (OT_OP_* bits, or the
+// gradient with at most one of interpolation and spreading).
+int run_pass(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
+             int mode, int accumulate, int32_t *ids, void *vel, void *fout, void *grad, hipStream_t s)
 {
     int rc = check_common(t, dtype, n, pos);
     if (rc) return rc;
-    if (ops <= 0 || ops > 7) return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
+    const bool ops_ok = (ops > 0 && ops <= 7) || ops == kOpGrad || ops == (kOpGrad | kOpInterp) ||
+                        ops == (kOpGrad | kOpSpread);
+    if (!ops_ok) return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
     if ((ops & kOpLocate) && n > 0 && !ids) return fail(OT_ERR_INVALID, "ids is NULL");
     if ((ops & kOpInterp) && ((n > 0 && !vel) || !field)) return fail(OT_ERR_INVALID, "field or vel is NULL");
+    if ((ops & kOpGrad) && ((n > 0 && (!grad || !force)) || !field))
+        return fail(OT_ERR_INVALID, "field, vector or gradient output is NULL");
     if (ops & kOpSpread) {
         if ((n > 0 && !force) || !fout) return fail(OT_ERR_INVALID, "force or field_out is NULL");
         if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
@@ -180,16 +183,27 @@ int track(const ot_tree *t, int ops, const void *field, const void *force, const
         const int64_t tile = (int64_t)threads * ppt;
         dim3 b(threads), g((unsigned)((n + tile - 1) / tile));
         if (dtype == OT_F32)
-            rc = mode == OT_SPREAD_FIXED ? dispatch_ops<float, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout)
-                                         : dispatch_ops<float, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout);
+            rc = mode == OT_SPREAD_FIXED
+                     ? dispatch_ops<float, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad)
+                     : dispatch_ops<float, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad);
         else
-            rc = mode == OT_SPREAD_FIXED ? dispatch_ops<double, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout)
-                                         : dispatch_ops<double, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout);
+            rc = mode == OT_SPREAD_FIXED
+                     ? dispatch_ops<double, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad)
+                     : dispatch_ops<double, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad);
         if (rc) return rc;
         OT_HIP(hipGetLastError());
     }
     if (ops & kOpSpread) return spread_epilogue(t, dtype, mode, accumulate, fout, s);
     return OT_OK;
+}
+
+}  // namespace
+
+int track(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
+          int mode, int accumulate, int32_t *ids, void *vel, void *fout, hipStream_t s)
+{
+    if (ops <= 0 || ops > 7) return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
+    return run_pass(t, ops, field, force, pos, dtype, n, mode, accumulate, ids, vel, fout, nullptr, s);
 }
 
 }  // namespace ot
@@ -226,18 +240,25 @@ extern "C" int ot_track(const ot_tree *t, int32_t ops, const void *field, const 
 extern "C" int ot_grad_pos(const ot_tree *t, const void *field, const void *vec, const void *pos, int32_t dtype,
                            int64_t n, void *grad, void *stream)
 {
-    int rc = check_common(t, dtype, n, pos);
-    if (rc) return rc;
-    if (n == 0) return OT_OK;
-    if (!field || !vec || !grad) return fail(OT_ERR_INVALID, "ot_grad_pos: NULL array");
-    dim3 b(256), g((unsigned)((n + 255) / 256));
-    hipStream_t s = (hipStream_t)stream;
-    if (dtype == OT_F32)
-        hipLaunchKernelGGL(k_grad<float>, g, b, 0, s, t->view, n, (const float *)pos, (const float *)field,
-                           (const float *)vec, (float *)grad);
-    else
-        hipLaunchKernelGGL(k_grad<double>, g, b, 0, s, t->view, n, (const double *)pos, (const double *)field,
-                           (const double *)vec, (double *)grad);
-    OT_HIP(hipGetLastError());
-    return OT_OK;
+    return run_pass(t, kOpGrad, field, vec, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, nullptr, nullptr, grad,
+                    (hipStream_t)stream);
+}
+
+extern "C" int ot_interp_backward(const ot_tree *t, const void *field, const void *grad_vel, const void *pos,
+                                  int32_t dtype, int64_t n, int32_t mode, int32_t accumulate, void *grad_field,
+                                  void *grad_pos, void *stream)
+{
+    const int ops = (grad_field ? (int)kOpSpread : 0) | (grad_pos ? (int)kOpGrad : 0);
+    if (!ops) return fail(OT_ERR_INVALID, "ot_interp_backward: both outputs are NULL");
+    return run_pass(t, ops, field, grad_vel, pos, dtype, n, mode, accumulate, nullptr, nullptr, grad_field, grad_pos,
+                    (hipStream_t)stream);
+}
+
+extern "C" int ot_spread_backward(const ot_tree *t, const void *grad_field, const void *force, const void *pos,
+                                  int32_t dtype, int64_t n, void *grad_force, void *grad_pos, void *stream)
+{
+    const int ops = (grad_force ? (int)kOpInterp : 0) | (grad_pos ? (int)kOpGrad : 0);
+    if (!ops) return fail(OT_ERR_INVALID, "ot_spread_backward: both outputs are NULL");
+    return run_pass(t, ops, grad_field, force, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, grad_force, nullptr,
+                    grad_pos, (hipStream_t)stream);
 }

@@ -11,6 +11,9 @@
 namespace ot {
 
 enum : int { kOpLocate = OT_OP_LOCATE, kOpInterp = OT_OP_INTERPOLATE, kOpSpread = OT_OP_SPREAD };
+// Internal op: position gradient grad[k] = sum_n (force[k] . field[leaf(n)])
+// grad_X w_kn, gathered with the same node lookups as the interpolation.
+enum : int { kOpGrad = 8 };
 enum : int { kModeAtomic = OT_SPREAD_ATOMIC, kModeFixed = OT_SPREAD_FIXED };
 
 // Fixed-point spreading state (lives in the tree's scratch buffer).
@@ -83,14 +86,6 @@ __device__ __forceinline__ void make_stencil(const TreeView &tv, const T X[3], c
             st.valid |= (ok ? 1u : 0u) << (d * 3 + o);
         }
     }
-}
-
-template <typename T>
-__device__ __forceinline__ uint32_t node_leaf(const TreeView &tv, const Stencil<T> &st, int ox, int oy, int oz)
-{
-    uint32_t e = __ldg(tv.table + (st.R[0][ox] | (st.R[1][oy] << 1) | (st.R[2][oz] << 2)));
-    if (e & kSplit) e = descend_below_root(tv, e, st.N[0][ox], st.N[1][oy], st.N[2][oz]);
-    return e & kIdMask;
 }
 
 // ---------------------------------------------------------------------------
@@ -276,12 +271,13 @@ struct LdsSink {
 // Point k: position pos[rs k + 0..2], force force[rs k + 0..2] (rs = 3 for
 // the caller's arrays, the record stride for sorted records).  With kv
 // (sorted points: host << 32 | input index) the per-point outputs go to the
-// input index.
+// input index.  With kOpGrad, force[k] is also the vector the gradient
+// contracts the field with, and the gradient goes to grad.
 template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const uint64_t *__restrict__ kv, int rs,
                                             const T *__restrict__ pos, const T *__restrict__ field,
                                             const T *__restrict__ force, int32_t *__restrict__ ids,
-                                            T *__restrict__ vel, Sink &sink)
+                                            T *__restrict__ vel, Sink &sink, T *__restrict__ grad = nullptr)
 {
     const int64_t kd = kv ? (int64_t)(uint32_t)kv[k] : k;
     const int64_t kp = (int64_t)rs * k;
@@ -290,9 +286,10 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
     const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
     const uint32_t e = ok ? descend(tv, I[0], I[1], I[2]) : 0u;
     if (OPS & kOpLocate) ids[kd] = ok ? (int32_t)(e & kIdMask) : -1;
-    if (!(OPS & (kOpInterp | kOpSpread))) return;
+    if (!(OPS & (kOpInterp | kOpSpread | kOpGrad))) return;
 
     T U[3] = {T(0), T(0), T(0)};
+    T G[3] = {T(0), T(0), T(0)};
     if (ok) {
         Stencil<T> st;
         make_stencil<T, PER>(tv, X, I, e, st);
@@ -320,18 +317,42 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
                 }
             }
         }
-        // phase 3: interpolation gathers
-        if (OPS & kOpInterp) {
+        // phase 3: field gathers (interpolation and/or the gradient)
+        if (OPS & (kOpInterp | kOpGrad)) {
+            // gradient: dw/dX_d = 2^l phi'(r_d) prod_{e != d} phi(r_e)
+            T dw[3][3];
+            T v[3] = {T(0), T(0), T(0)};
+            if (OPS & kOpGrad) {
+                const T sc = (T)(1 << st.level);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const T s = X[d] * sc;
+                    T wtmp[3];
+                    delta3_grad<T>(s - floor(s), wtmp, dw[d]);
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) dw[d][o] *= sc;
+                    v[d] = force[kp + d];
+                }
+            }
 #pragma unroll
             for (int q = 0; q < 27; ++q) {
                 const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
                 const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
                 if (!PER && (st.valid & need) != need) continue;
                 const int64_t j = 3 * (int64_t)(ent[q] & kIdMask);
-                const T w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
-                U[0] = fma(w, field[j], U[0]);
-                U[1] = fma(w, field[j + 1], U[1]);
-                U[2] = fma(w, field[j + 2], U[2]);
+                const T f0 = field[j], f1 = field[j + 1], f2 = field[j + 2];
+                if (OPS & kOpInterp) {
+                    const T w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
+                    U[0] = fma(w, f0, U[0]);
+                    U[1] = fma(w, f1, U[1]);
+                    U[2] = fma(w, f2, U[2]);
+                }
+                if (OPS & kOpGrad) {
+                    const T dot = fma(v[0], f0, fma(v[1], f1, v[2] * f2));
+                    G[0] = fma(dot * dw[0][ox], st.w[1][oy] * st.w[2][oz], G[0]);
+                    G[1] = fma(dot * st.w[0][ox], dw[1][oy] * st.w[2][oz], G[1]);
+                    G[2] = fma(dot * st.w[0][ox], st.w[1][oy] * dw[2][oz], G[2]);
+                }
             }
         }
         // phase 4: spreading
@@ -340,6 +361,7 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
             // sink the interpolation sums below the spreading and keep all
             // 27 gathered values alive through it
             if (OPS & kOpInterp) asm volatile("" : "+v"(U[0]), "+v"(U[1]), "+v"(U[2]));
+            if (OPS & kOpGrad) asm volatile("" : "+v"(G[0]), "+v"(G[1]), "+v"(G[2]));
             const T F[3] = {force[kp], force[kp + 1], force[kp + 2]};
             uint32_t live = (1u << 27) - 1u;
             if (!PER) {
@@ -358,56 +380,11 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
         vel[3 * kd + 1] = U[1];
         vel[3 * kd + 2] = U[2];
     }
-}
-
-// grad[k,d] = sum_n (vec_k . field[leaf(n)]) 2^l phi'(r_d) prod_{e!=d} phi(r_e)
-template <typename T>
-__device__ __forceinline__ void grad_point(const TreeView &tv, int64_t k, const T *__restrict__ pos,
-                                           const T *__restrict__ field, const T *__restrict__ vec,
-                                           T *__restrict__ grad)
-{
-    const T X[3] = {pos[3 * k], pos[3 * k + 1], pos[3 * k + 2]};
-    uint32_t I[3];
-    const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
-    T G[3] = {T(0), T(0), T(0)};
-    if (ok) {
-        const uint32_t e = descend(tv, I[0], I[1], I[2]);
-        Stencil<T> st;
-        if (tv.periodic) make_stencil<T, true>(tv, X, I, e, st);
-        else make_stencil<T, false>(tv, X, I, e, st);
-        T dw[3][3];
-        const T sc = (T)(1 << st.level);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T s = X[d] * sc;
-            T wtmp[3];
-            delta3_grad<T>(s - floor(s), wtmp, dw[d]);
-#pragma unroll
-            for (int o = 0; o < 3; ++o) dw[d][o] *= sc;
-        }
-        const T v0 = vec[3 * k], v1 = vec[3 * k + 1], v2 = vec[3 * k + 2];
-#pragma unroll
-        for (int oz = 0; oz < 3; ++oz) {
-#pragma unroll
-            for (int oy = 0; oy < 3; ++oy) {
-#pragma unroll
-                for (int ox = 0; ox < 3; ++ox) {
-                    const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
-                    if ((st.valid & need) != need) continue;
-                    const uint32_t leaf = (ox == 1 && oy == 1 && oz == 1) ? st.host : node_leaf<T>(tv, st, ox, oy, oz);
-                    const int64_t j = 3 * (int64_t)leaf;
-                    const T dot = fma(v0, field[j], fma(v1, field[j + 1], v2 * field[j + 2]));
-                    const T wyz = st.w[1][oy] * st.w[2][oz];
-                    G[0] = fma(dot * dw[0][ox], wyz, G[0]);
-                    G[1] = fma(dot * st.w[0][ox], dw[1][oy] * st.w[2][oz], G[1]);
-                    G[2] = fma(dot * st.w[0][ox], st.w[1][oy] * dw[2][oz], G[2]);
-                }
-            }
-        }
+    if (OPS & kOpGrad) {
+        grad[3 * kd] = G[0];
+        grad[3 * kd + 1] = G[1];
+        grad[3 * kd + 2] = G[2];
     }
-    grad[3 * k] = G[0];
-    grad[3 * k + 1] = G[1];
-    grad[3 * k + 2] = G[2];
 }
 
 template <typename T>
@@ -490,10 +467,11 @@ template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, int64_t end,
                                             const uint64_t *__restrict__ kv, int rs, const T *__restrict__ pos,
                                             const T *__restrict__ field, const T *__restrict__ force,
-                                            int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink)
+                                            int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink,
+                                            T *__restrict__ grad = nullptr)
 {
     for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x)
-        track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink);
+        track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink, grad);
 }
 
 // LDS table size of the aggregating sink, per precision and mode

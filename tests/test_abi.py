@@ -86,3 +86,16 @@ def test_migration_host_side_validation(ot):
 def test_particle_step_host_side_validation(ot):
     L = ot.lib
     assert L.ot_particle_step(None, None, None, None, None, None, None, 0, 1, None, None) == -1
+
+
+def test_backward_host_side_validation(ot):
+    L = ot.lib
+    dummy = ctypes.c_void_p(0x1000)
+    # both outputs NULL: nothing to compute
+    assert L.ot_interp_backward(dummy, dummy, dummy, dummy, 0, 10, 1, 0, None, None, None) == -1
+    assert b"both outputs are NULL" in L.ot_last_error()
+    assert L.ot_spread_backward(dummy, dummy, dummy, dummy, 0, 10, None, None, None) == -1
+    # no tree
+    assert L.ot_interp_backward(None, dummy, dummy, dummy, 0, 10, 1, 0, dummy, dummy, None) == -1
+    assert b"tree is NULL" in L.ot_last_error()
+    assert L.ot_spread_backward(None, dummy, dummy, dummy, 0, 10, dummy, None, None) == -1

@@ -296,6 +296,84 @@ def test_grad_pos_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
     assert scaled_err(got, g, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_interp_backward_one_pass_cfg1(ot, cfg1, cfg1_gpu, dtype):
+    """Backward of interpolation in one pass: the field's gradient is the
+    spreading of the upstream gradient, the positions' the phi' contraction.
+    The per-point arithmetic is that of the separate passes (FIXED spreading
+    is order independent), so both outputs match them bit for bit."""
+    w, o = cfg1
+    pts, g, fld = _inputs(w, o, dtype)
+    P, G, Fd = to_dev(pts, dtype), to_dev(g, dtype), to_dev(fld, dtype)
+    gf, gx = cfg1_gpu.interp_backward(Fd, G, P, mode="fixed")
+    assert torch.equal(gf, cfg1_gpu.spread(G, P, mode="fixed"))
+    assert torch.equal(gx, cfg1_gpu.grad_pos(Fd, G, P))
+    want, S = o.grad_pos(fld, g, pts, with_scale=True)
+    assert scaled_err(gx.cpu().numpy(), want, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
+    f, Sf, cnt, A = o.spread(g, pts, with_scale=True)
+    assert spread_excess(gf.cpu().numpy(), f, Sf, A, cnt, dtype, fixed_point_quantum(g)) <= 1.0
+    # one output at a time, and accumulation into the field's gradient
+    gf1, none = cfg1_gpu.interp_backward(Fd, G, P, mode="fixed", need_pos=False)
+    assert none is None and torch.equal(gf1, gf)
+    none, gx1 = cfg1_gpu.interp_backward(Fd, G, P, need_field=False)
+    assert none is None and torch.equal(gx1, gx)
+    acc = gf.clone()
+    cfg1_gpu.interp_backward(Fd, G, P, mode="fixed", need_pos=False, accumulate=True, grad_field=acc)
+    assert torch.equal(acc, 2 * gf)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_spread_backward_one_pass_cfg1(ot, cfg1, cfg1_gpu, dtype):
+    """Backward of spreading in one pass: the forces' gradient is the
+    interpolation of the field's gradient, the positions' the phi'
+    contraction with the forces."""
+    w, o = cfg1
+    pts, frc, _ = _inputs(w, o, dtype)
+    gfield = as_dtype(np.random.default_rng(8).standard_normal((o.n_leaves, 3)), dtype)
+    P, F, Gf = to_dev(pts, dtype), to_dev(frc, dtype), to_dev(gfield, dtype)
+    gF, gx = cfg1_gpu.spread_backward(Gf, F, P)
+    assert torch.equal(gF, cfg1_gpu.interpolate(Gf, P))
+    assert torch.equal(gx, cfg1_gpu.grad_pos(Gf, F, P))
+    U, S = o.interpolate(gfield, pts, with_scale=True)
+    assert scaled_err(gF.cpu().numpy(), U, S) <= TOL[dtype]
+    want, S = o.grad_pos(gfield, frc, pts, with_scale=True)
+    assert scaled_err(gx.cpu().numpy(), want, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
+    gF1, none = cfg1_gpu.spread_backward(Gf, F, P, need_pos=False)
+    assert none is None and torch.equal(gF1, gF)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_backward_one_pass_nonperiodic(ot, dtype):
+    """Both backward passes with walls (nodes outside dropped) on a deep tree."""
+    spec = synth.band_tree(2, 9, [synth.Sphere((0.3, 0.6, 0.5), 0.2), synth.Sphere((0.8, 0.2, 0.15), 0.1)],
+                           periodic=False, seed=5)
+    t, o = gpu_tree(spec), oracle_tree(spec)
+    rng = np.random.default_rng(9)
+    pts = as_dtype(np.concatenate([synth.fibonacci_sphere(synth.Sphere((0.3, 0.6, 0.5), 0.2), 3000, wrap=False),
+                                   rng.random((3000, 3)), _extra_points(rng, 9, 300)]), dtype)
+    g = as_dtype(rng.standard_normal(pts.shape), dtype)
+    fld = as_dtype(rng.standard_normal((spec.n_leaves, 3)), dtype)
+    P, G, Fd = to_dev(pts, dtype), to_dev(g, dtype), to_dev(fld, dtype)
+    gf, gx = t.interp_backward(Fd, G, P, mode="atomic")
+    f, Sf, cnt, A = o.spread(g, pts, with_scale=True)
+    assert spread_excess(gf.cpu().numpy(), f, Sf, A, cnt, dtype) <= 1.0
+    want, S = o.grad_pos(fld, g, pts, with_scale=True)
+    assert scaled_err(gx.cpu().numpy(), want, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
+    gF, gx2 = t.spread_backward(Fd, G, P)     # the same contraction: field with the vectors G
+    assert torch.equal(gx2, gx)
+    U, S = o.interpolate(fld, pts, with_scale=True)
+    assert scaled_err(gF.cpu().numpy(), U, S) <= TOL[dtype]
+
+
+def test_backward_empty_input(ot, cfg1_gpu):
+    P = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    Fd = torch.ones((cfg1_gpu.n_leaves, 3), dtype=torch.float32, device="cuda")
+    gf, gx = cfg1_gpu.interp_backward(Fd, P, P, mode="fixed")
+    assert torch.count_nonzero(gf) == 0 and gx.numel() == 0
+    gF, gx = cfg1_gpu.spread_backward(Fd, P, P)
+    assert gF.numel() == 0 and gx.numel() == 0
+
+
 # ---------------------------------------------------------------------------
 # Batched persistent pass
 # ---------------------------------------------------------------------------
