@@ -83,6 +83,12 @@ extern "C" {
 #define OT_OP_LOCATE      1   /* write host ids                       */
 #define OT_OP_INTERPOLATE 2   /* write interpolated velocities        */
 #define OT_OP_SPREAD      4   /* spread forces into the leaf field    */
+/* Position gradient grad[k] = sum_n (force[k] . field[leaf(n)]) dw_kn/dX
+ * (as ot_grad_pos with vec = force).  Batched plans only, alone or with one
+ * of OT_OP_INTERPOLATE (backward of spreading: field = dLoss/dfield_out,
+ * force = the forward forces) and OT_OP_SPREAD (backward of interpolation:
+ * field = the forward field, force = dLoss/dvel); run with ot_batch_run_grad. */
+#define OT_OP_GRAD_POS    8
 
 typedef struct ot_tree ot_tree;
 typedef struct ot_batch_plan ot_batch_plan;
@@ -191,7 +197,8 @@ int ot_grad_pos(const ot_tree *tree, const void *field, const void *vec, const v
  *   grad_field (+)= spread(grad_vel)            (as ot_spread, mode/accumulate)
  *   grad_pos    = ot_grad_pos(field, grad_vel)   (host leaf held fixed).
  * field: (n_leaves, 3) forward field; grad_vel: (n, 3) dLoss/dvel.  Either
- * output may be NULL (not computed), not both.  grad_field: (n_leaves, 3);
+ * output may be NULL (not computed), not both unless n = 0 (then the call
+ * only clears grad_field when given and accumulate = 0).  grad_field: (n_leaves, 3);
  * grad_pos: (n, 3).  Uses the tree's workspace in FIXED mode, like
  * ot_spread.  Errors: OT_ERR_INVALID for NULL inputs that an output needs,
  * a bad mode or dtype, n < 0. */
@@ -203,8 +210,8 @@ int ot_interp_backward(const ot_tree *tree, const void *field, const void *grad_
  *   grad_force = interpolate(grad_field)          (as ot_interpolate)
  *   grad_pos   = ot_grad_pos(grad_field, force)   (host leaf held fixed).
  * grad_field: (n_leaves, 3) dLoss/dfield_out; force: (n, 3) forward forces.
- * Either output may be NULL, not both; both are (n, 3) and overwritten.
- * Errors as ot_interp_backward. */
+ * Either output may be NULL, not both unless n = 0 (then nothing is done);
+ * both are (n, 3) and overwritten.  Errors as ot_interp_backward. */
 int ot_spread_backward(const ot_tree *tree, const void *grad_field, const void *force, const void *pos,
                        int32_t dtype, int64_t n, void *grad_force, void *grad_pos, void *stream);
 
@@ -316,6 +323,15 @@ int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets, const int3
  * later runs with the same set replay it. */
 int ot_batch_run(ot_batch_plan *plan, const void *field, const void *force, const void *pos,
                  int32_t *ids, void *vel, void *field_out, void *stream);
+
+/* Run a plan whose instances carry OT_OP_GRAD_POS (ops 8, 10 or 12 each; a
+ * plan does not mix them with forward-only ops): as ot_batch_run, and the
+ * position gradient of every such point goes to grad ((n, 3) dtype).  With
+ * point sorting the per-point vector (force) travels with the positions.
+ * Errors: OT_ERR_INVALID for NULL arrays the ops need, or a plan without
+ * gradient ops; ot_batch_run refuses plans with them. */
+int ot_batch_run_grad(ot_batch_plan *plan, const void *field, const void *force, const void *pos,
+                      int32_t *ids, void *vel, void *field_out, void *grad, void *stream);
 
 /* Timing of the persistent kernel: with enable = 1, ot_batch_run enqueues
  * the plan's sequence directly on the caller's stream (not through the

@@ -22,7 +22,7 @@ LIB_PATH = os.environ.get("OCTRACK_LIB") or os.path.join(_HERE, "libocttrack.so"
 OT_OK = 0
 OT_F32, OT_F64 = 0, 1
 OT_SPREAD_ATOMIC, OT_SPREAD_FIXED = 0, 1
-OT_OP_LOCATE, OT_OP_INTERPOLATE, OT_OP_SPREAD = 1, 2, 4
+OT_OP_LOCATE, OT_OP_INTERPOLATE, OT_OP_SPREAD, OT_OP_GRAD_POS = 1, 2, 4, 8
 
 ERRORS = {-1: "OT_ERR_INVALID", -2: "OT_ERR_NOT_PARTITION", -3: "OT_ERR_UNSORTED_DUP",
           -4: "OT_ERR_LEVEL_RANGE", -5: "OT_ERR_OOM", -6: "OT_ERR_HIP", -7: "OT_ERR_CAPACITY"}
@@ -64,7 +64,7 @@ EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_g
            "ot_batch_run", "ot_batch_plan_shape", "ot_batch_plan_timing", "ot_batch_last_kernel_ms",
            "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums",
            "ot_relocate", "ot_leaf_splitters", "ot_find_owner", "ot_particle_step", "ot_interp_backward",
-           "ot_spread_backward")
+           "ot_spread_backward", "ot_batch_run_grad")
 
 
 def _load():
@@ -88,6 +88,7 @@ def _load():
         "ot_spread_backward": [P, P, P, P, i32, i64, P, P, P],
         "ot_batch_plan_create": [P, P, P, i32, i32, i32, ctypes.POINTER(Tuning), ctypes.POINTER(P)],
         "ot_batch_run": [P, P, P, P, P, P, P, P],
+        "ot_batch_run_grad": [P, P, P, P, P, P, P, P, P],
         "ot_batch_plan_shape": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
         "ot_batch_plan_timing": [P, i32],
         "ot_batch_last_kernel_ms": [P, ctypes.POINTER(ctypes.c_float)],
@@ -465,6 +466,7 @@ class BatchPlan:
         self.tree = tree
         self.n_points = int(offsets[-1])
         self.dtype = dtype
+        self.grad_ops = any(int(v) & OT_OP_GRAD_POS for v in ops)
 
     def shape(self) -> Tuple[int, int]:
         nt, g = ctypes.c_int64(), ctypes.c_int32()
@@ -479,7 +481,9 @@ class BatchPlan:
         _check(lib.ot_batch_last_kernel_ms(self._h, ctypes.byref(v)))
         return float(v.value)
 
-    def run(self, pos, field=None, force=None, ids=None, vel=None, field_out=None):
+    def run(self, pos, field=None, force=None, ids=None, vel=None, field_out=None, grad=None):
+        """One pass; `grad` receives the position gradient of plans with OT_OP_GRAD_POS ops (force is then
+        the per-point vector the gradient contracts the field with)."""
         n, nl = self.n_points, self.tree.n_leaves
         _check_out(pos, n, self.dtype, None, "pos")
         _check_out(force, n, self.dtype, None, "force")
@@ -487,6 +491,13 @@ class BatchPlan:
         _check_out(field_out, nl, self.dtype, None, "field_out")
         _check_out(vel, n, self.dtype, None, "vel")
         _check_out(ids, n, torch.int32, None, "ids")
+        _check_out(grad, n, self.dtype, None, "grad")
+        if self.grad_ops:
+            _check(lib.ot_batch_run_grad(self._h, _ptr(field), _ptr(force), _ptr(pos), _ptr(ids), _ptr(vel),
+                                         _ptr(field_out), _ptr(grad), _stream()))
+            return ids, vel, field_out, grad
+        if grad is not None:
+            raise ValueError("grad is only written by plans with OT_OP_GRAD_POS ops")
         _check(lib.ot_batch_run(self._h, _ptr(field), _ptr(force), _ptr(pos), _ptr(ids), _ptr(vel),
                                 _ptr(field_out), _stream()))
         return ids, vel, field_out

@@ -35,13 +35,14 @@ struct ot_batch_plan {
     bool have_graph;
     hipGraph_t graph;
     hipGraphExec_t exec;
-    const void *key[6];
+    const void *key[7];
     bool timing;              // record ev[0]/ev[1] around the persistent kernel
     hipEvent_t ev[2];
     // point sorting (OT_TUNE_SORT_POINTS)
     bool sort_points;
     int sort_bits, sort_shift;
     int ops_all;              // the common ops of every instance
+    bool grad_plan;           // instances carry OT_OP_GRAD_POS
     uint64_t *skv[2];         // host << 32 | input index, in sorted order
     void *srec[2];            // position (+ force) records in sorted order
     void *sws;                // counting workspace
@@ -54,14 +55,16 @@ constexpr uint32_t kCountMask = 0x00FFFFFFu;
 constexpr int kSortKeyBits = 16;   // two 8-bit passes
 
 
-template <typename T, int MODE, bool PER>
+// GRAD: the plan's ops are gradient passes (8, 10, 12), else forward (1..7).
+template <typename T, int MODE, bool PER, bool GRAD>
 __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__restrict__ tile_start,
                                                const uint32_t *__restrict__ tile_info, int64_t n_tiles,
                                                unsigned *__restrict__ counter, const uint64_t *__restrict__ kv,
                                                int rs, const T *__restrict__ pos,
                                                const T *__restrict__ field, const T *__restrict__ force,
                                                int32_t *__restrict__ ids, T *__restrict__ vel, T *__restrict__ fout,
-                                               unsigned long long *__restrict__ facc, const FxState *__restrict__ fx)
+                                               unsigned long long *__restrict__ facc, const FxState *__restrict__ fx,
+                                               T *__restrict__ grad)
 {
     constexpr int S = SinkSlots<T, MODE>::value;
     using Acc = typename AccType<T, MODE>::type;
@@ -80,12 +83,22 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
         const int64_t start = tile_start[tile];
         const uint32_t info = tile_info[tile];
         const int64_t end = start + (int64_t)(info & kCountMask);
-        switch (info >> 24) {
+        if constexpr (!GRAD) {
+            switch (info >> 24) {
 #define OT_CASE(OPSV) \
     case OPSV: track_range<T, OPSV, PER>(tv, start, end, kv, rs, pos, field, force, ids, vel, sink); break;
-            OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
+                OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
 #undef OT_CASE
-        default: break;
+            default: break;
+            }
+        } else {
+            switch (info >> 24) {
+#define OT_CASE(OPSV) \
+    case OPSV: track_range<T, OPSV, PER>(tv, start, end, kv, rs, pos, field, force, ids, vel, sink, grad); break;
+                OT_CASE(kOpGrad) OT_CASE(kOpGrad | kOpInterp) OT_CASE(kOpGrad | kOpSpread)
+#undef OT_CASE
+            default: break;
+            }
         }
         sink.flush();   // one spatially coherent tile per table fill
     }
@@ -93,7 +106,7 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
 
 template <typename T, int MODE>
 int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids, void *vel,
-            void *fout, hipStream_t s)
+            void *fout, void *grad, hipStream_t s)
 {
     const ot_tree *t = p->tree;
     const int64_t n = p->n_points;
@@ -109,11 +122,12 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
     if (p->sort_points && n > 0) {
         // ids come from the key pass; positions and forces travel with the
         // keys, and the first pass takes max |F| on the way
-        const bool carry_force = (p->ops_all & kOpSpread) != 0;
+        const bool carry_force = (p->ops_all & (kOpSpread | kOpGrad)) != 0;
         PointSortBufs<T> b{{p->skv[0], p->skv[1]}, {(T *)p->srec[0], (T *)p->srec[1]}, p->sws};
         PointSortResult<T> r;
-        unsigned long long *maxbits =
-            (carry_force && p->mode == OT_SPREAD_FIXED) ? &((FxState *)t->scratch)->maxbits : nullptr;
+        unsigned long long *maxbits = ((p->ops_all & kOpSpread) && p->mode == OT_SPREAD_FIXED)
+                                          ? &((FxState *)t->scratch)->maxbits
+                                          : nullptr;
         point_sort<T>(t->view, n, t->n_leaves, p->sort_shift, p->sort_bits, (const T *)pos,
                       carry_force ? (const T *)force : nullptr, (p->ops_all & kOpLocate) ? ids : nullptr, b, maxbits,
                       s, r);
@@ -126,12 +140,18 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
     }
     if (spread && (rc = spread_scale(t, p->dtype, p->mode, scale_from, n, s))) return rc;
     if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
-    if (t->view.periodic)
-        hipLaunchKernelGGL((k_batch<T, MODE, true>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start,
-                           p->tile_info, p->n_tiles, p->counter, kv, rs, kpos, (const T *)field, kforce, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
-    else
-        hipLaunchKernelGGL((k_batch<T, MODE, false>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start,
-                           p->tile_info, p->n_tiles, p->counter, kv, rs, kpos, (const T *)field, kforce, kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch);
+#define OT_KBATCH(PERV, GRADV)                                                                                     \
+    hipLaunchKernelGGL((k_batch<T, MODE, PERV, GRADV>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start, \
+                       p->tile_info, p->n_tiles, p->counter, kv, rs, kpos, (const T *)field, kforce, kids, (T *)vel,  \
+                       (T *)fout, t->fx_acc, (const FxState *)t->scratch, (T *)grad)
+    if (p->grad_plan) {
+        if (t->view.periodic) OT_KBATCH(true, true);
+        else OT_KBATCH(false, true);
+    } else {
+        if (t->view.periodic) OT_KBATCH(true, false);
+        else OT_KBATCH(false, false);
+    }
+#undef OT_KBATCH
     OT_HIP(hipGetLastError());
     if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
     if (p->ops_union & kOpSpread)
@@ -141,13 +161,18 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
 }
 
 int enqueue_any(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids, void *vel,
-                void *fout, hipStream_t s)
+                void *fout, void *grad, hipStream_t s)
 {
     if (p->dtype == OT_F32)
-        return p->mode == OT_SPREAD_FIXED ? enqueue<float, kModeFixed>(p, field, force, pos, ids, vel, fout, s)
-                                          : enqueue<float, kModeAtomic>(p, field, force, pos, ids, vel, fout, s);
-    return p->mode == OT_SPREAD_FIXED ? enqueue<double, kModeFixed>(p, field, force, pos, ids, vel, fout, s)
-                                      : enqueue<double, kModeAtomic>(p, field, force, pos, ids, vel, fout, s);
+        return p->mode == OT_SPREAD_FIXED ? enqueue<float, kModeFixed>(p, field, force, pos, ids, vel, fout, grad, s)
+                                          : enqueue<float, kModeAtomic>(p, field, force, pos, ids, vel, fout, grad, s);
+    return p->mode == OT_SPREAD_FIXED ? enqueue<double, kModeFixed>(p, field, force, pos, ids, vel, fout, grad, s)
+                                      : enqueue<double, kModeAtomic>(p, field, force, pos, ids, vel, fout, grad, s);
+}
+
+bool valid_ops(int o)
+{
+    return (o >= 0 && o <= 7) || o == kOpGrad || o == (kOpGrad | kOpInterp) || o == (kOpGrad | kOpSpread);
 }
 
 void drop_graph(ot_batch_plan *p)
@@ -172,6 +197,12 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     if (!tree || !offsets || !ops || n_inst <= 0) return fail(OT_ERR_INVALID, "ot_batch_plan_create: bad arguments");
     if (dtype != OT_F32 && dtype != OT_F64) return fail(OT_ERR_INVALID, "dtype must be OT_F32 or OT_F64");
     if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
+    int kinds = 0;   // bit 0: forward-only ops, bit 1: gradient ops
+    for (int i = 0; i < n_inst; ++i) {
+        if (!valid_ops(ops[i])) return fail(OT_ERR_INVALID, "bad per-instance ops");
+        if (ops[i]) kinds |= (ops[i] & kOpGrad) ? 2 : 1;
+    }
+    if (kinds == 3) return fail(OT_ERR_INVALID, "gradient and forward-only ops cannot share a plan");
     const bool sort_points = tuning && (tuning->flags & OT_TUNE_SORT_POINTS);
     // defaults: 512 threads and 4 points per thread, narrower and shorter
     // tiles when there are too few points for two workgroups per CU
@@ -192,7 +223,6 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     int ops_union = 0, ops_all = -1;
     for (int i = 0; i < n_inst; ++i) {
         if (offsets[i + 1] < offsets[i]) return fail(OT_ERR_INVALID, "offsets must be ascending");
-        if (ops[i] < 0 || ops[i] > 7) return fail(OT_ERR_INVALID, "bad per-instance ops");
         if (ops[i] == 0 || offsets[i + 1] == offsets[i]) continue;
         ops_union |= ops[i];
         if (ops_all >= 0 && ops_all != ops[i] && sort_points)
@@ -228,13 +258,14 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     p->have_graph = false;
     p->sort_points = sort_points;
     p->ops_all = ops_all;
+    p->grad_plan = (ops_union & kOpGrad) != 0;
     if (sort_points && p->n_points > 0) {
         const int64_t n = p->n_points;
         int bits = 1;
         while ((int64_t(1) << bits) <= tree->n_leaves) ++bits;   // keys go up to n_leaves
         p->sort_shift = std::max(0, bits - kSortKeyBits);
         p->sort_bits = bits - p->sort_shift;
-        const size_t rec = ((ops_all & kOpSpread) ? 6 : 3) * (size_t)n * (dtype == OT_F32 ? 4 : 8);
+        const size_t rec = ((ops_all & (kOpSpread | kOpGrad)) ? 6 : 3) * (size_t)n * (dtype == OT_F32 ? 4 : 8);
         hipError_t e = hipSuccess;
         for (int i = 0; i < 2 && e == hipSuccess; ++i) {
             e = hipMalloc((void **)&p->skv[i], 8 * (size_t)n);
@@ -252,10 +283,17 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per_cu = 0;
-    const void *kfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? (const void *)k_batch<float, kModeFixed, true>
-                                                                 : (const void *)k_batch<float, kModeAtomic, true>)
-                                      : (mode == OT_SPREAD_FIXED ? (const void *)k_batch<double, kModeFixed, true>
-                                                                 : (const void *)k_batch<double, kModeAtomic, true>);
+    const void *kfn;
+    if (p->grad_plan)
+        kfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? (const void *)k_batch<float, kModeFixed, true, true>
+                                                         : (const void *)k_batch<float, kModeAtomic, true, true>)
+                              : (mode == OT_SPREAD_FIXED ? (const void *)k_batch<double, kModeFixed, true, true>
+                                                         : (const void *)k_batch<double, kModeAtomic, true, true>);
+    else
+        kfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? (const void *)k_batch<float, kModeFixed, true, false>
+                                                         : (const void *)k_batch<float, kModeAtomic, true, false>)
+                              : (mode == OT_SPREAD_FIXED ? (const void *)k_batch<double, kModeFixed, true, false>
+                                                         : (const void *)k_batch<double, kModeAtomic, true, false>);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, block, 0);
     if (per_cu <= 0) per_cu = 1;
     int grid = tuning && tuning->grid ? tuning->grid : std::max(1, cus) * per_cu;
@@ -287,26 +325,29 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     return OT_OK;
 }
 
-extern "C" int ot_batch_run(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids,
-                            void *vel, void *field_out, void *stream)
+namespace ot {
+namespace {
+
+int run_plan(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids, void *vel,
+             void *field_out, void *grad, void *stream)
 {
-    if (!p) return fail(OT_ERR_INVALID, "plan is NULL");
     const int u = p->ops_union;
     if (p->n_points > 0 && !pos) return fail(OT_ERR_INVALID, "pos is NULL");
     if ((u & kOpLocate) && !ids) return fail(OT_ERR_INVALID, "ids is NULL");
     if ((u & kOpInterp) && (!field || !vel)) return fail(OT_ERR_INVALID, "field or vel is NULL");
     if ((u & kOpSpread) && (!force || !field_out)) return fail(OT_ERR_INVALID, "force or field_out is NULL");
+    if ((u & kOpGrad) && (!field || !force || !grad)) return fail(OT_ERR_INVALID, "field, force or grad is NULL");
     hipStream_t s = (hipStream_t)stream;
     if (p->timing) {
         // Events recorded inside a captured graph cannot be timed, so a timed
         // run enqueues the same sequence directly on the caller's stream.
-        return enqueue_any(p, field, force, pos, ids, vel, field_out, s);
+        return enqueue_any(p, field, force, pos, ids, vel, field_out, grad, s);
     }
-    const void *key[6] = {field, force, pos, ids, vel, field_out};
+    const void *key[7] = {field, force, pos, ids, vel, field_out, grad};
     if (!p->have_graph || std::memcmp(key, p->key, sizeof(key)) != 0) {
         drop_graph(p);
         OT_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
-        int rc = enqueue_any(p, field, force, pos, ids, vel, field_out, p->capture_stream);
+        int rc = enqueue_any(p, field, force, pos, ids, vel, field_out, grad, p->capture_stream);
         hipGraph_t g = nullptr;
         hipError_t ec = hipStreamEndCapture(p->capture_stream, &g);
         if (rc) {
@@ -327,6 +368,25 @@ extern "C" int ot_batch_run(ot_batch_plan *p, const void *field, const void *for
     }
     OT_HIP(hipGraphLaunch(p->exec, s));
     return OT_OK;
+}
+
+}  // namespace
+}  // namespace ot
+
+extern "C" int ot_batch_run(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids,
+                            void *vel, void *field_out, void *stream)
+{
+    if (!p) return fail(OT_ERR_INVALID, "plan is NULL");
+    if (p->grad_plan) return fail(OT_ERR_INVALID, "plan has gradient ops: run it with ot_batch_run_grad");
+    return run_plan(p, field, force, pos, ids, vel, field_out, nullptr, stream);
+}
+
+extern "C" int ot_batch_run_grad(ot_batch_plan *p, const void *field, const void *force, const void *pos,
+                                 int32_t *ids, void *vel, void *field_out, void *grad, void *stream)
+{
+    if (!p) return fail(OT_ERR_INVALID, "plan is NULL");
+    if (!p->grad_plan) return fail(OT_ERR_INVALID, "plan has no gradient ops: run it with ot_batch_run");
+    return run_plan(p, field, force, pos, ids, vel, field_out, grad, stream);
 }
 
 extern "C" int ot_batch_plan_shape(const ot_batch_plan *p, int64_t *n_tiles, int32_t *grid)

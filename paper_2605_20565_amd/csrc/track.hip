@@ -248,8 +248,12 @@ extern "C" int ot_interp_backward(const ot_tree *t, const void *field, const voi
                                   int32_t dtype, int64_t n, int32_t mode, int32_t accumulate, void *grad_field,
                                   void *grad_pos, void *stream)
 {
-    const int ops = (grad_field ? (int)kOpSpread : 0) | (grad_pos ? (int)kOpGrad : 0);
-    if (!ops) return fail(OT_ERR_INVALID, "ot_interp_backward: both outputs are NULL");
+    int ops = (grad_field ? (int)kOpSpread : 0) | (grad_pos ? (int)kOpGrad : 0);
+    if (n == 0) ops &= ~(int)kOpGrad;   // no points: no position gradient (grad_field is still cleared)
+    if (!ops) {
+        if (n == 0) return check_common(t, dtype, n, pos);
+        return fail(OT_ERR_INVALID, "ot_interp_backward: both outputs are NULL");
+    }
     return run_pass(t, ops, field, grad_vel, pos, dtype, n, mode, accumulate, nullptr, nullptr, grad_field, grad_pos,
                     (hipStream_t)stream);
 }
@@ -258,6 +262,7 @@ extern "C" int ot_spread_backward(const ot_tree *t, const void *grad_field, cons
                                   int32_t dtype, int64_t n, void *grad_force, void *grad_pos, void *stream)
 {
     const int ops = (grad_force ? (int)kOpInterp : 0) | (grad_pos ? (int)kOpGrad : 0);
+    if (n == 0) return check_common(t, dtype, n, pos);   // both outputs are per point: nothing to do
     if (!ops) return fail(OT_ERR_INVALID, "ot_spread_backward: both outputs are NULL");
     return run_pass(t, ops, grad_field, force, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, grad_force, nullptr,
                     grad_pos, (hipStream_t)stream);

@@ -11,9 +11,9 @@
 namespace ot {
 
 enum : int { kOpLocate = OT_OP_LOCATE, kOpInterp = OT_OP_INTERPOLATE, kOpSpread = OT_OP_SPREAD };
-// Internal op: position gradient grad[k] = sum_n (force[k] . field[leaf(n)])
-// grad_X w_kn, gathered with the same node lookups as the interpolation.
-enum : int { kOpGrad = 8 };
+// Position gradient grad[k] = sum_n (force[k] . field[leaf(n)]) grad_X w_kn,
+// gathered with the same node lookups as the interpolation.
+enum : int { kOpGrad = OT_OP_GRAD_POS };
 enum : int { kModeAtomic = OT_SPREAD_ATOMIC, kModeFixed = OT_SPREAD_FIXED };
 
 // Fixed-point spreading state (lives in the tree's scratch buffer).

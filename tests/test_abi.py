@@ -99,3 +99,15 @@ def test_backward_host_side_validation(ot):
     assert L.ot_interp_backward(None, dummy, dummy, dummy, 0, 10, 1, 0, dummy, dummy, None) == -1
     assert b"tree is NULL" in L.ot_last_error()
     assert L.ot_spread_backward(None, dummy, dummy, dummy, 0, 10, dummy, None, None) == -1
+    # no points: nothing per point to compute, whatever the outputs
+    assert L.ot_spread_backward(dummy, dummy, dummy, None, 0, 0, None, None, None) == 0
+
+
+def test_batch_gradient_ops_host_side_validation(ot):
+    L = ot.lib
+    h = ctypes.c_void_p()
+    off = (ctypes.c_int64 * 3)(0, 5, 9)
+    for bad in ((9, 9), (14, 14), (16, 16), (7, 8), (12, 3)):   # not gradient sets / mixed with forward ops
+        ops = (ctypes.c_int32 * 2)(*bad)
+        assert L.ot_batch_plan_create(ctypes.c_void_p(0x1000), off, ops, 2, 0, 0, None, ctypes.byref(h)) == -1
+    assert L.ot_batch_run_grad(None, None, None, None, None, None, None, None, None) == -1

@@ -421,6 +421,85 @@ def test_batch_matches_plain_launches(ot, cfg1, cfg1_gpu, dtype):
         plan.close()
 
 
+@pytest.mark.parametrize("sort", [False, True])
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_gradient_plans_match_one_pass(ot, cfg1, cfg1_gpu, dtype, sort):
+    """Batched gradient passes, with the points sorted by host or not, equal
+    the one-pass backward entries bit for bit: FIXED spreading does not
+    depend on the order, and every point's sums are formed the same way."""
+    w, o = cfg1
+    pts, g, fld = _inputs(w, o, dtype, extra=False)
+    P, G, Fd = to_dev(pts, dtype), to_dev(g, dtype), to_dev(fld, dtype)
+    n, nl = P.shape[0], cfg1_gpu.n_leaves
+    off = [0, 1000, 1500, 1507, 4000, n]
+    # backward of interpolation: spread the upstream gradient, and the position gradient
+    ops = [ot.OT_OP_SPREAD | ot.OT_OP_GRAD_POS] * 5
+    plan = ot.BatchPlan(cfg1_gpu, off, ops, dtype=dtype, mode="fixed", sort_points=sort, block=128, tile=256)
+    gf = torch.empty((nl, 3), dtype=dtype, device="cuda")
+    gx = torch.full((n, 3), -7.0, dtype=dtype, device="cuda")
+    ref_f, ref_x = cfg1_gpu.interp_backward(Fd, G, P, mode="fixed")
+    for _ in range(2):   # capture, then replay
+        plan.run(P, field=Fd, force=G, field_out=gf, grad=gx)
+        torch.cuda.synchronize()
+        assert torch.equal(gf, ref_f)
+        assert torch.equal(gx, ref_x)
+    plan.close()
+    # backward of spreading: interpolate the field's gradient, and the position gradient
+    plan = ot.BatchPlan(cfg1_gpu, off, [ot.OT_OP_INTERPOLATE | ot.OT_OP_GRAD_POS] * 5, dtype=dtype,
+                        sort_points=sort, block=128, tile=256)
+    gF = torch.empty((n, 3), dtype=dtype, device="cuda")
+    gx2 = torch.empty((n, 3), dtype=dtype, device="cuda")
+    plan.run(P, field=Fd, force=G, vel=gF, grad=gx2)
+    ref_F, ref_x2 = cfg1_gpu.spread_backward(Fd, G, P)
+    assert torch.equal(gF, ref_F)
+    assert torch.equal(gx2, ref_x2)
+    plan.close()
+
+
+def test_batch_gradient_plan_mixed_instances(ot, cfg1, cfg1_gpu):
+    """Unsorted gradient plans may mix the three gradient op sets per
+    instance; ot_batch_run and ot_batch_run_grad refuse the other kind."""
+    w, o = cfg1
+    dtype = torch.float64
+    pts, g, fld = _inputs(w, o, dtype, extra=False)
+    P, G, Fd = to_dev(pts, dtype), to_dev(g, dtype), to_dev(fld, dtype)
+    n, nl = P.shape[0], cfg1_gpu.n_leaves
+    off = [0, 1000, 1500, 1507, 4000, n]
+    GP, I, S = ot.OT_OP_GRAD_POS, ot.OT_OP_INTERPOLATE, ot.OT_OP_SPREAD
+    ops = [GP | S, GP, GP | I, GP | S, GP | I]
+    plan = ot.BatchPlan(cfg1_gpu, off, ops, dtype=dtype, mode="atomic")
+    vel = torch.full((n, 3), -7.0, dtype=dtype, device="cuda")
+    fo = torch.empty((nl, 3), dtype=dtype, device="cuda")
+    gx = torch.empty((n, 3), dtype=dtype, device="cuda")
+    plan.run(P, field=Fd, force=G, vel=vel, field_out=fo, grad=gx)
+    torch.cuda.synchronize()
+    assert torch.equal(gx, cfg1_gpu.grad_pos(Fd, G, P))
+    ref_vel = cfg1_gpu.interpolate(Fd, P)
+    rows = torch.zeros(n, dtype=torch.bool)
+    for i, op in enumerate(ops):
+        a, b = off[i], off[i + 1]
+        if op & I:
+            assert torch.equal(vel[a:b], ref_vel[a:b])
+        else:
+            assert (vel[a:b] == -7).all()
+        if op & S:
+            rows[a:b] = True
+    m = rows.numpy()
+    f, Sf, cnt, A = o.spread(g[m], pts[m], with_scale=True)
+    assert spread_excess(fo.cpu().numpy(), f, Sf, A, cnt, dtype) <= 1.0
+    with pytest.raises(ot.OtError):
+        ot._check(ot.lib.ot_batch_run(plan._h, ot._ptr(Fd), ot._ptr(G), ot._ptr(P), None, ot._ptr(vel),
+                                      ot._ptr(fo), ot._stream()))
+    plan.close()
+    fwd = ot.BatchPlan(cfg1_gpu, off, [7] * 5, dtype=dtype)
+    with pytest.raises(ot.OtError):
+        ot._check(ot.lib.ot_batch_run_grad(fwd._h, ot._ptr(Fd), ot._ptr(G), ot._ptr(P), None, ot._ptr(vel),
+                                           ot._ptr(fo), ot._ptr(gx), ot._stream()))
+    fwd.close()
+    with pytest.raises(ot.OtError):   # gradient and forward-only ops in one plan
+        ot.BatchPlan(cfg1_gpu, off, [7, GP, 7, 7, 7], dtype=dtype)
+
+
 def test_batch_graph_replays_are_identical(ot, cfg1, cfg1_gpu):
     w, o = cfg1
     pts, frc, fld = _inputs(w, o, torch.float32, extra=False)
