@@ -143,7 +143,12 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     __shared__ uint32_t dcount[kBuckets];
     __shared__ unsigned long long sh_max[kThreads / 64];
 
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    // Workgroups go round-robin over the 8 XCDs; each XCD takes a contiguous
+    // range of tiles, so the ends of neighbouring tiles' digit runs (partial
+    // cache lines) meet in the same L2.
+    const int xg = (int)(blockIdx.x & 7u), xk = (int)(blockIdx.x >> 3), xq = nblocks >> 3, xr = nblocks & 7;
+    const int tile = xg * xq + (xg < xr ? xg : xr) + xk;
+    const int64_t base = (int64_t)tile * kTile;
     const int64_t rem = n - base;
     const int valid = rem < kTile ? (int)rem : kTile;
     for (int d = threadIdx.x; d < kBuckets; d += kThreads) dcount[d] = 0;
@@ -209,7 +214,7 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
             const uint32_t key = sk[pad(i)];
             const int64_t src = base + si[pad(i)];
             const uint32_t d = (key >> shift) & (kBuckets - 1);
-            const int64_t dst = (int64_t)offs[(int64_t)d * nblocks + blockIdx.x] + (i - (int)dstart[d]);
+            const int64_t dst = (int64_t)offs[(int64_t)d * nblocks + tile] + (i - (int)dstart[d]);
             kout[dst] = ((uint64_t)key << 32) | (uint32_t)kin[src];
             T v[R];
             if (rin) {
