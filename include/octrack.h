@@ -66,8 +66,10 @@ extern "C" {
 #define OT_F32 0
 #define OT_F64 1
 
-/* Spreading accumulation.  ATOMIC: atomic adds in the working precision
- * (FP32 or FP64), order dependent in the last bits.  FIXED: every
+/* Spreading accumulation.  ATOMIC: atomic adds, order dependent in the last
+ * bits; workgroups sum their points' contributions in FP64 (for FP32 inputs
+ * the exact products) and add each partial sum to field_out with one atomic
+ * in the working precision (FP32 or FP64).  FIXED: every
  * contribution is rounded once to a signed 64-bit fixed-point value
  * q = rint(w F 2^s), ties to even, formed with one FP64 fused multiply-add
  * (exact product for FP32 inputs, the exact FP64 product rounded once for
@@ -107,7 +109,7 @@ typedef struct {
     int64_t workspace_bytes; /* device bytes of the fixed-point spreading workspace   */
 } ot_tree_info;
 
-/* Tuning of the batched persistent pass.  Zero fields take defaults: 512
+/* Tuning of the batched persistent pass.  Zero fields take defaults: 256
  * threads and 4 points per thread, narrowed (down to 64 threads, 1 point
  * per thread) when the run has too few points for two workgroups per CU. */
 typedef struct {

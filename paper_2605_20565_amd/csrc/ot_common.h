@@ -82,18 +82,28 @@ __host__ __device__ __forceinline__ uint32_t compact3_21(uint64_t v)
     return (uint32_t)v;
 }
 
+// Descent-table entry i.  The table pointer reaches kernels inside
+// TreeView, where the compiler cannot tell its address space and emits flat
+// loads; a flat load counts against the LDS counter as well, so every wait
+// for an LDS result would also wait for the table loads in flight.  Read it
+// as global memory.
+__device__ __forceinline__ uint32_t ld_table(const TreeView &tv, int64_t i)
+{
+    return ((const __attribute__((address_space(1))) uint32_t *)tv.table)[i];
+}
+
 // Table entry of the leaf containing the finest-level cell (ix, iy, iz).
 __device__ __forceinline__ uint32_t descend(const TreeView &tv, uint32_t ix, uint32_t iy,
                                             uint32_t iz)
 {
     int sh = tv.L - tv.lev[0];
-    uint32_t e = __ldg(tv.table + interleave3(ix >> sh, iy >> sh, iz >> sh));
+    uint32_t e = ld_table(tv, interleave3(ix >> sh, iy >> sh, iz >> sh));
     for (int t = 1; t < tv.nlev && (e & kSplit); ++t) {
         int d = tv.lev[t] - tv.lev[t - 1];
         int s = tv.L - tv.lev[t];
         uint32_t m = (1u << d) - 1u;
         uint32_t sub = interleave3((ix >> s) & m, (iy >> s) & m, (iz >> s) & m);
-        e = __ldg(tv.table + tv.off[t] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
+        e = ld_table(tv, tv.off[t] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
     }
     return e;
 }

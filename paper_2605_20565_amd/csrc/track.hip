@@ -177,7 +177,7 @@ int run_pass(const ot_tree *t, int ops, const void *field, const void *force, co
         // (their time is latency, not throughput); large ones up to
         // kMaxPointsPerThread points per thread.
         const int64_t want = 2 * (int64_t)t->cus;
-        int threads = (ops & kOpSpread) ? 512 : 256;
+        int threads = 256;
         while (threads > 64 && (n + threads - 1) / threads < want) threads >>= 1;
         const int64_t ppt = std::max<int64_t>(1, std::min<int64_t>(kMaxPointsPerThread, n / ((int64_t)threads * want)));
         const int64_t tile = (int64_t)threads * ppt;

@@ -36,7 +36,7 @@ __device__ __forceinline__ uint32_t descend_below_root(const TreeView &tv, uint3
         const int s = tv.L - tv.lev[t];
         const uint32_t m = (1u << d) - 1u;
         const uint32_t sub = interleave3((ix >> s) & m, (iy >> s) & m, (iz >> s) & m);
-        e = __ldg(tv.table + tv.off[t] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
+        e = ld_table(tv, tv.off[t] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
     }
     return e;
 }
@@ -91,8 +91,13 @@ __device__ __forceinline__ void make_stencil(const TreeView &tv, const T X[3], c
 // ---------------------------------------------------------------------------
 // Spreading sinks: where the contributions w F of one point go.
 // ---------------------------------------------------------------------------
+// Accumulator of one contribution and of the workgroup tables: int64 fixed
+// point, or FP64 in ATOMIC mode for both precisions.  FP32 contributions
+// are the exact FP64 products of their FP32 factors and are rounded to FP32
+// once per table slot, at the device-memory add (LDS FP32 atomic adds run
+// several times slower than 64-bit ones on this target).
 template <typename T, int MODE>
-struct AccType { using type = T; };
+struct AccType { using type = double; };
 template <typename T>
 struct AccType<T, kModeFixed> { using type = unsigned long long; };
 
@@ -113,15 +118,22 @@ template <typename T, int MODE>
 __device__ __forceinline__ typename AccType<T, MODE>::type to_acc(T w, T f, double scale)
 {
     if constexpr (MODE == kModeFixed) return fx_round_fma((double)w, (double)f * scale);
-    else return w * f;
+    else return (double)w * (double)f;
 }
 
+// Device-memory adds of the sinks, through global-address-space pointers
+// (the sinks hold fout/facc in structs, where the compiler would emit flat
+// atomics, which also count against the LDS counter).
 template <typename T, int MODE>
 __device__ __forceinline__ void global_add(T *fout, unsigned long long *facc, int64_t j,
                                            typename AccType<T, MODE>::type v)
 {
-    if constexpr (MODE == kModeFixed) atomicAdd(facc + j, v);
-    else atomic_add(fout + j, v);
+    if constexpr (MODE == kModeFixed)
+        __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long *)(facc + j), v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_fetch_add((__attribute__((address_space(1))) T *)(fout + j), (T)v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Straight to device memory with one atomic per component.
@@ -302,7 +314,7 @@ __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const
             const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
             if (q == 13) ent[q] = st.host | ((uint32_t)st.level << kLevelShift);
             else if (!PER && (st.valid & need) != need) ent[q] = 0u;
-            else ent[q] = __ldg(tv.table + (st.R[0][ox] | (st.R[1][oy] << 1) | (st.R[2][oz] << 2)));
+            else ent[q] = ld_table(tv, st.R[0][ox] | (st.R[1][oy] << 1) | (st.R[2][oz] << 2));
         }
         // phase 2: nodes inside split root cells continue the descent (rare)
         uint32_t any = 0u;
@@ -474,9 +486,8 @@ __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, i
         track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink, grad);
 }
 
-// LDS table size of the aggregating sink, per precision and mode
-// (FIXED and FP64 slots hold 3 x 8 bytes, FP32 atomic slots 3 x 4 bytes).
+// LDS table size of the aggregating sink (every slot holds 3 x 8 bytes).
 template <typename T, int MODE>
-struct SinkSlots { static constexpr int value = (MODE == kModeFixed || sizeof(T) == 8) ? 2048 : 4096; };
+struct SinkSlots { static constexpr int value = 2048; };
 
 }  // namespace ot
