@@ -227,10 +227,16 @@ int ot_spread_backward(const ot_tree *tree, const void *grad_field, const void *
  * their prescribed velocities.  force_lag (nullable, (n, 3)) receives the
  * sum over the iterations of F_k, force_eul (nullable, (n_leaves, 3)) the sum
  * of f (the total forcing of the time step).  work: caller-owned device
- * buffer of ot_mdf_workspace_bytes(tree, n, dtype) bytes; the call allocates
- * nothing.  Uses the tree's spreading workspace in FIXED mode (calls on one
- * tree must not run concurrently).  Errors: OT_ERR_INVALID (null arrays,
- * n < 0, n_iter < 0, dt or rho not positive, bad mode/dtype), OT_ERR_HIP. */
+ * buffer of ot_mdf_workspace_bytes(tree, n, dtype) bytes, 8-byte aligned;
+ * the call allocates nothing and enqueues kernels only (no memset), so it
+ * can be captured in a graph.  Once per call the markers are sorted by host
+ * leaf and the leaves their stencils reach are listed; the iterations run
+ * over the sorted markers and clear, convert and update only the listed
+ * leaves (results as in input order; FIXED bitwise so).  At most 2^31 - 1
+ * markers (OT_ERR_CAPACITY).  Uses the tree's spreading workspace in FIXED mode
+ * (calls on one tree must not run concurrently).  Errors: OT_ERR_INVALID
+ * (null arrays, n < 0, n_iter < 0, dt or rho not positive, bad mode/dtype,
+ * misaligned work), OT_ERR_HIP. */
 int64_t ot_mdf_workspace_bytes(const ot_tree *tree, int64_t n, int32_t dtype);
 
 /* Per-body sums of the IBM coupling (Sec. 2.3, fully resolved bodies).  For

@@ -17,8 +17,9 @@ namespace ot {
 namespace {
 
 // One workgroup per tile of `tile` consecutive points.  Spreading goes
-// through the workgroup's LDS aggregation table, flushed once at the end.
-template <typename T, int OPS, int MODE, bool PER>
+// through the workgroup's LDS aggregation table of S slots, flushed once at
+// the end.
+template <typename T, int OPS, int MODE, bool PER, int S>
 __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t tile, const T *__restrict__ pos,
                                                const T *__restrict__ field, const T *__restrict__ force,
                                                int32_t *__restrict__ ids, T *__restrict__ vel,
@@ -28,7 +29,6 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
     const int64_t start = (int64_t)blockIdx.x * tile;
     const int64_t end = start + tile < n ? start + tile : n;
     if constexpr ((OPS & kOpSpread) != 0) {
-        constexpr int S = SinkSlots<T, MODE>::value;
         using Acc = typename AccType<T, MODE>::type;
         __shared__ uint32_t keys[S];
         __shared__ Acc vals[LdsSink<T, MODE, S>::kVals];
@@ -45,6 +45,25 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
 }
 
 constexpr int kMaxPointsPerThread = 4;
+// Tiles of at most kSmallTile points spread through a table of kSmallSlots
+// slots (14 KiB instead of 56 KiB of LDS): such launches are many small
+// workgroups whose time is latency, and the large table would hold the CU
+// to two of them (measured on 11 k points: 76 -> 63 us per fused launch;
+// tiles of 128 bubble markers already reach more leaves than 512 slots).
+constexpr int64_t kSmallTile = 64;
+constexpr int kSmallSlots = 512;
+
+template <typename T, int OPS, int MODE, int S>
+void launch_track(const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStream_t s, int64_t n, const T *P, const T *Fd,
+                  const T *Fo, int32_t *ids, T *V, T *O, const FxState *fx, T *Gr)
+{
+    if (t->view.periodic)
+        hipLaunchKernelGGL((k_track<T, OPS, MODE, true, S>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,
+                           t->fx_acc, fx, Gr);
+    else
+        hipLaunchKernelGGL((k_track<T, OPS, MODE, false, S>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,
+                           t->fx_acc, fx, Gr);
+}
 
 template <typename T, int MODE>
 int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStream_t s, int64_t n, const void *pos,
@@ -53,13 +72,14 @@ int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStr
     const T *P = (const T *)pos, *Fd = (const T *)field, *Fo = (const T *)force;
     T *V = (T *)vel, *O = (T *)fout, *Gr = (T *)grad;
     const FxState *fx = (const FxState *)t->scratch;
-#define OT_LAUNCH(OPSV)                                                                                         \
-    if (t->view.periodic)                                                                                        \
-        hipLaunchKernelGGL((k_track<T, OPSV, MODE, true>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,    \
-                           t->fx_acc, fx, Gr);                                                                   \
+    constexpr int kSlots = SinkSlots<T, MODE>::value;
+    const bool small = tile <= kSmallTile;
+#define OT_LAUNCH(OPSV)                                                                                          \
+    if (small)                                                                                                   \
+        launch_track<T, OPSV, MODE, ((OPSV) & kOpSpread) ? kSmallSlots : kSlots>(t, g, b, tile, s, n, P, Fd, Fo,  \
+                                                                                ids, V, O, fx, Gr);               \
     else                                                                                                         \
-        hipLaunchKernelGGL((k_track<T, OPSV, MODE, false>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,   \
-                           t->fx_acc, fx, Gr);                                                                   \
+        launch_track<T, OPSV, MODE, kSlots>(t, g, b, tile, s, n, P, Fd, Fo, ids, V, O, fx, Gr);                   \
     break;
     switch (ops) {
     case 1: OT_LAUNCH(1)
@@ -152,25 +172,11 @@ int check_common(const ot_tree *t, int dtype, int64_t n, const void *pos)
 
 namespace {
 
-// One pass over the points with the ops in `ops` (OT_OP_* bits, or the
-// gradient with at most one of interpolation and spreading).
-int run_pass(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
-             int mode, int accumulate, int32_t *ids, void *vel, void *fout, void *grad, hipStream_t s)
+// The pass's kernel alone, no clearing, scale or conversion around it.
+int launch_ops(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
+               int mode, int32_t *ids, void *vel, void *fout, void *grad, hipStream_t s)
 {
-    int rc = check_common(t, dtype, n, pos);
-    if (rc) return rc;
-    const bool ops_ok = (ops > 0 && ops <= 7) || ops == kOpGrad || ops == (kOpGrad | kOpInterp) ||
-                        ops == (kOpGrad | kOpSpread);
-    if (!ops_ok) return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
-    if ((ops & kOpLocate) && n > 0 && !ids) return fail(OT_ERR_INVALID, "ids is NULL");
-    if ((ops & kOpInterp) && ((n > 0 && !vel) || !field)) return fail(OT_ERR_INVALID, "field or vel is NULL");
-    if ((ops & kOpGrad) && ((n > 0 && (!grad || !force)) || !field))
-        return fail(OT_ERR_INVALID, "field, vector or gradient output is NULL");
-    if (ops & kOpSpread) {
-        if ((n > 0 && !force) || !fout) return fail(OT_ERR_INVALID, "force or field_out is NULL");
-        if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
-        if ((rc = spread_prologue(t, dtype, mode, accumulate, force, n, fout, s))) return rc;
-    }
+    int rc = OT_OK;
     if (n > 0) {
         // Enough workgroups to give every CU two, when there are points for
         // them: small sets get narrower workgroups and one point per thread
@@ -193,11 +199,43 @@ int run_pass(const ot_tree *t, int ops, const void *field, const void *force, co
         if (rc) return rc;
         OT_HIP(hipGetLastError());
     }
+    return OT_OK;
+}
+
+// One pass over the points with the ops in `ops` (OT_OP_* bits, or the
+// gradient with at most one of interpolation and spreading).
+int run_pass(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
+             int mode, int accumulate, int32_t *ids, void *vel, void *fout, void *grad, hipStream_t s)
+{
+    int rc = check_common(t, dtype, n, pos);
+    if (rc) return rc;
+    const bool ops_ok = (ops > 0 && ops <= 7) || ops == kOpGrad || ops == (kOpGrad | kOpInterp) ||
+                        ops == (kOpGrad | kOpSpread);
+    if (!ops_ok) return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
+    if ((ops & kOpLocate) && n > 0 && !ids) return fail(OT_ERR_INVALID, "ids is NULL");
+    if ((ops & kOpInterp) && ((n > 0 && !vel) || !field)) return fail(OT_ERR_INVALID, "field or vel is NULL");
+    if ((ops & kOpGrad) && ((n > 0 && (!grad || !force)) || !field))
+        return fail(OT_ERR_INVALID, "field, vector or gradient output is NULL");
+    if (ops & kOpSpread) {
+        if ((n > 0 && !force) || !fout) return fail(OT_ERR_INVALID, "force or field_out is NULL");
+        if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
+        if ((rc = spread_prologue(t, dtype, mode, accumulate, force, n, fout, s))) return rc;
+    }
+    if ((rc = launch_ops(t, ops, field, force, pos, dtype, n, mode, ids, vel, fout, grad, s))) return rc;
     if (ops & kOpSpread) return spread_epilogue(t, dtype, mode, accumulate, fout, s);
     return OT_OK;
 }
 
 }  // namespace
+
+// Spreading kernel alone into fout (ATOMIC) or the fixed-point accumulators
+// (FIXED): the caller has cleared what it reads back and, in FIXED mode,
+// prepared the scale (spread_scale).
+int spread_kernel(const ot_tree *t, int dtype, int mode, const void *force, const void *pos, int64_t n, void *fout,
+                  hipStream_t s)
+{
+    return launch_ops(t, kOpSpread, nullptr, force, pos, dtype, n, mode, nullptr, nullptr, fout, nullptr, s);
+}
 
 int track(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
           int mode, int accumulate, int32_t *ids, void *vel, void *fout, hipStream_t s)

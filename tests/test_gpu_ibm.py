@@ -120,3 +120,44 @@ def test_mdf_inplace_and_zero_iterations(ot):
     assert torch.equal(u, keep) and not fl.any() and not fe.any()
     u, _, _ = t.mdf(field, pos, tgt, 2, inplace=True)
     assert u.data_ptr() == field.data_ptr() and not torch.equal(field, keep)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_mdf_touched_leaves_equal_dense_composition(ot, dtype):
+    """The iterations update only the leaves the markers' stencils reach;
+    in FIXED mode the result equals, bit for bit, the dense composition of
+    the library's interpolation and spreading with the elementwise steps in
+    torch (the same IEEE operations in the same order)."""
+    w = synth.workload(1)
+    markers = w.points[:w.instances[1]]
+    sph = w.spheres[0]
+    pos = to_dev(as_dtype(markers, dtype), dtype)
+    target = to_dev(as_dtype(_rigid_targets(markers, sph.centre), dtype), dtype)
+    o = oracle_tree(w.tree)
+    t = gpu_tree(w.tree)
+    u0 = to_dev(as_dtype(o.permute_rows(w.field), dtype), dtype)
+    n_iter, dt, rho = 4, 0.5, 2.0
+    ug, flg, feg = t.mdf(u0, pos, target, n_iter, dt, rho, mode="fixed")
+    u = u0.clone()
+    fl = torch.zeros_like(pos)
+    fe = torch.zeros_like(u0)
+    for _ in range(n_iter):
+        F = (target - t.interpolate(u, pos)) / dt
+        f = t.spread(F, pos, mode="fixed")
+        u = u + f / rho
+        fl = fl + F
+        fe = fe + f
+    assert torch.equal(ug, u)
+    assert torch.equal(flg, fl)
+    assert torch.equal(feg, fe)
+    # leaves no marker reaches are untouched
+    far = (fe == 0).all(dim=1)
+    assert int(far.sum()) > 0 and torch.equal(ug[far], u0[far])
+    # a second call with the same workspace (the list is rebuilt per call)
+    work = torch.empty(int(ot.lib.ot_mdf_workspace_bytes(t.handle, pos.shape[0], 0 if dtype == torch.float32 else 1)),
+                       dtype=torch.uint8, device="cuda")
+    ua, _, _ = t.mdf(u0, pos, target, n_iter, dt, rho, mode="fixed", work=work)
+    ub, _, _ = t.mdf(u0, pos[:100], target[:100], n_iter, dt, rho, mode="fixed", work=work)
+    assert torch.equal(ua, ug)
+    uc, _, _ = t.mdf(u0, pos[:100], target[:100], n_iter, dt, rho, mode="fixed")
+    assert torch.equal(ub, uc)
