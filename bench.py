@@ -242,7 +242,7 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        extra = side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot, torch)
+        extra = side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot, torch, shape)
 
     if args.presorted:
         log("[bench] presorted input: not the headline layout")
@@ -254,7 +254,7 @@ def main():
                    "point_order": "host-leaf order (pre-sorted)" if args.presorted else "random (as generated)",
                    "path": "batched persistent kernel, HIP graph" + (", in-step sort of points by host leaf"
                                                                       if shape["sort_points"] else ""),
-                   "block": shape["block"] or 512, "tile": shape["tile"] or 4 * (shape["block"] or 512),
+                   "block": shape["block"] or "library default", "tile": shape["tile"] or "library default",
                    "tiles": n_tiles, "workgroups": grid, "autotuned": not args.no_tune},
         "roofline": roofline,
     }
@@ -275,7 +275,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot, torch):
+def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot, torch, shape):
     res = {}
     n = pos.shape[0]
 
@@ -301,6 +301,14 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
                          "path": "one fused launch per step"}
     ms_main = timeit(step, max(3, args.steps // 2))
     res["speedup_vs_fp64_plain"] = round(ms64 / ms_main, 3)
+    # the batched path in FP64 (FIXED, sorted), same launch shape as the measured step
+    pl64 = ot.BatchPlan(tree, [int(v) for v in w.instances], [7] * (len(w.instances) - 1), dtype=torch.float64,
+                        mode="fixed", block=shape["block"], tile=shape["tile"], grid=shape["grid"],
+                        sort_points=shape["sort_points"])
+    ms64b = timeit(lambda: pl64.run(p64, field=fl64, force=f64, ids=i64, vel=v64, field_out=o64),
+                   max(3, args.steps // 2))
+    pl64.close()
+    res["fp64_batched"] = {"ms_per_step": round(ms64b, 4), "value": n / (ms64b * 1e-3), "spread_mode": "fixed"}
     del p64, f64, fl64, i64, v64, o64
 
     # one plain fused launch per instance (the alternative to one batched pass)
