@@ -120,7 +120,8 @@ typedef struct {
 } ot_tuning;
 
 /* Sort the points by host leaf before the persistent pass: locate, then
- * two stable radix passes over the top 16 bits of the host ids that carry
+ * stable 8-bit radix passes over the host ids down to groups of at most 64
+ * consecutive ids (two passes up to 4 M leaves, three above) that carry
  * positions and forces into plan-owned buffers; the pass then visits the
  * points in that order and writes each result at its point's input row.
  * Neighbouring threads then share stencil nodes in cache and in the

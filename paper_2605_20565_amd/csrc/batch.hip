@@ -52,7 +52,6 @@ namespace ot {
 namespace {
 
 constexpr uint32_t kCountMask = 0x00FFFFFFu;
-constexpr int kSortKeyBits = 16;   // two 8-bit passes
 
 
 // GRAD: the plan's ops are gradient passes (8, 10, 12), else forward (1..7).
@@ -263,10 +262,7 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     p->grad_plan = (ops_union & kOpGrad) != 0;
     if (sort_points && p->n_points > 0) {
         const int64_t n = p->n_points;
-        int bits = 1;
-        while ((int64_t(1) << bits) <= tree->n_leaves) ++bits;   // keys go up to n_leaves
-        p->sort_shift = std::max(0, bits - kSortKeyBits);
-        p->sort_bits = bits - p->sort_shift;
+        point_sort_key_bits(tree->n_leaves, p->sort_shift, p->sort_bits);
         const size_t rec = ((ops_all & (kOpSpread | kOpGrad)) ? 6 : 3) * (size_t)n * (dtype == OT_F32 ? 4 : 8);
         hipError_t e = hipSuccess;
         for (int i = 0; i < 2 && e == hipSuccess; ++i) {

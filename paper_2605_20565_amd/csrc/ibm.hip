@@ -196,13 +196,12 @@ int mdf(const ot_tree *t, T *field, const T *pos, const T *target, int64_t n, in
         return OT_OK;
     }
     const int dtype = sizeof(T) == 4 ? OT_F32 : OT_F64;
-    // markers sorted by host leaf (groups of up to 2^16 leaf-id ranges), once
-    int bits = 1;
-    while ((int64_t(1) << bits) <= t->n_leaves) ++bits;   // keys go up to n_leaves
-    const int shift = std::max(0, bits - 16);
+    // markers sorted by host leaf, once
+    int shift, bits;
+    point_sort_key_bits(t->n_leaves, shift, bits);
     PointSortBufs<T> sb{{w.kv[0], w.kv[1]}, {(T *)w.rec[0], (T *)w.rec[1]}, w.sws};
     PointSortResult<T> sr;
-    point_sort<T>(t->view, n, t->n_leaves, shift, bits - shift, pos, (const T *)nullptr, (int32_t *)nullptr, sb,
+    point_sort<T>(t->view, n, t->n_leaves, shift, bits, pos, (const T *)nullptr, (int32_t *)nullptr, sb,
                   (unsigned long long *)nullptr, s, sr);
     const uint64_t *kv = sr.kv;
     pos = sr.rec;   // sorted positions, (n, 3)

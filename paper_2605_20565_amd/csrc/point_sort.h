@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "ot_common.h"
@@ -25,6 +27,20 @@ struct PointSortResult {
 };
 
 int64_t point_sort_ws_bytes(int64_t n);
+
+// Key bits [shift, shift + bits) to sort by for a tree of n_leaves leaves
+// (keys run up to n_leaves): groups of at most 64 consecutive leaf ids, and
+// all of the id when it has at most 16 bits.  Trees of up to 4 M leaves
+// take two 8-bit passes, larger ones three (measured on 17 M and 20 M
+// leaves: groups of 512 leaves left a tile's points spread over more leaves
+// than the spreading table holds; 64 beat 8 and 2 as well).
+inline void point_sort_key_bits(int64_t n_leaves, int &shift, int &bits)
+{
+    int all = 1;
+    while ((int64_t(1) << all) <= n_leaves) ++all;
+    shift = std::max(0, std::min(6, all - 16));
+    bits = all - shift;
+}
 
 // Keys (host leaf ids; points without a host get n_leaves), ids when
 // ids != null, then ceil(bits / 8) stable passes over key bits

@@ -6,8 +6,8 @@
 // table, and positions and forces are read with coalesced loads.  Each point
 // is one 64-bit word host << 32 | input index plus one record of R values
 // (position, then force when spreading).  The passes order by key bits
-// [shift, shift + bits) only (groups of 2^shift consecutive leaves, at most
-// two 8-bit LSD passes).
+// [shift, shift + bits) only (groups of 2^shift consecutive leaves; 8-bit
+// LSD passes, see point_sort_key_bits).
 //
 // A pass takes tiles of 2048 points: the keys are staged in LDS with
 // coalesced loads, ranked stably by the digit with eight 1-bit splits, and
