@@ -43,6 +43,7 @@ struct ot_batch_plan {
     int sort_bits, sort_shift;
     int ops_all;              // the common ops of every instance
     bool grad_plan;           // instances carry OT_OP_GRAD_POS
+    bool small_table;         // tiles of at most kSmallTile points: the small spreading table
     uint64_t *skv[2];         // host << 32 | input index, in sorted order
     void *srec[2];            // position (+ force) records in sorted order
     void *sws;                // counting workspace
@@ -55,7 +56,8 @@ constexpr uint32_t kCountMask = 0x00FFFFFFu;
 
 
 // GRAD: the plan's ops are gradient passes (8, 10, 12), else forward (1..7).
-template <typename T, int MODE, bool PER, bool GRAD>
+// S: slots of the workgroup's spreading table.
+template <typename T, int MODE, bool PER, bool GRAD, int S>
 __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__restrict__ tile_start,
                                                const uint32_t *__restrict__ tile_info, int64_t n_tiles,
                                                unsigned *__restrict__ counter, const uint64_t *__restrict__ kv,
@@ -65,7 +67,6 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
                                                unsigned long long *__restrict__ facc, const FxState *__restrict__ fx,
                                                T *__restrict__ grad)
 {
-    constexpr int S = SinkSlots<T, MODE>::value;
     using Acc = typename AccType<T, MODE>::type;
     __shared__ uint32_t keys[S];
     __shared__ Acc vals[LdsSink<T, MODE, S>::kVals];
@@ -139,10 +140,15 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
     }
     if (spread && (rc = spread_scale(t, p->dtype, p->mode, scale_from, n, s))) return rc;
     if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
+#define OT_KBATCH_S(PERV, GRADV, SV)                                                                               \
+    hipLaunchKernelGGL((k_batch<T, MODE, PERV, GRADV, SV>), dim3(p->grid), dim3(p->block), 0, s, t->view,            \
+                       p->tile_start, p->tile_info, p->n_tiles, p->counter, kv, rs, kpos, (const T *)field, kforce,  \
+                       kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch, (T *)grad)
 #define OT_KBATCH(PERV, GRADV)                                                                                     \
-    hipLaunchKernelGGL((k_batch<T, MODE, PERV, GRADV>), dim3(p->grid), dim3(p->block), 0, s, t->view, p->tile_start, \
-                       p->tile_info, p->n_tiles, p->counter, kv, rs, kpos, (const T *)field, kforce, kids, (T *)vel,  \
-                       (T *)fout, t->fx_acc, (const FxState *)t->scratch, (T *)grad)
+    do {                                                                                                           \
+        if (p->small_table) OT_KBATCH_S(PERV, GRADV, kSmallSlots);                                                \
+        else OT_KBATCH_S(PERV, GRADV, (SinkSlots<T, MODE>::value));                                                \
+    } while (0)
     if (p->grad_plan) {
         if (t->view.periodic) OT_KBATCH(true, true);
         else OT_KBATCH(false, true);
@@ -151,6 +157,7 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
         else OT_KBATCH(false, false);
     }
 #undef OT_KBATCH
+#undef OT_KBATCH_S
     OT_HIP(hipGetLastError());
     if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
     if (p->ops_union & kOpSpread)
@@ -167,6 +174,15 @@ int enqueue_any(ot_batch_plan *p, const void *field, const void *force, const vo
                                           : enqueue<float, kModeAtomic>(p, field, force, pos, ids, vel, fout, grad, s);
     return p->mode == OT_SPREAD_FIXED ? enqueue<double, kModeFixed>(p, field, force, pos, ids, vel, fout, grad, s)
                                       : enqueue<double, kModeAtomic>(p, field, force, pos, ids, vel, fout, grad, s);
+}
+
+// The persistent kernel of a plan (for the occupancy query).
+template <typename T, int MODE>
+const void *kbatch_fn(bool grad, bool small)
+{
+    constexpr int L = SinkSlots<T, MODE>::value;
+    if (grad) return small ? (const void *)k_batch<T, MODE, true, true, kSmallSlots> : (const void *)k_batch<T, MODE, true, true, L>;
+    return small ? (const void *)k_batch<T, MODE, true, false, kSmallSlots> : (const void *)k_batch<T, MODE, true, false, L>;
 }
 
 bool valid_ops(int o)
@@ -281,17 +297,12 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int per_cu = 0;
-    const void *kfn;
-    if (p->grad_plan)
-        kfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? (const void *)k_batch<float, kModeFixed, true, true>
-                                                         : (const void *)k_batch<float, kModeAtomic, true, true>)
-                              : (mode == OT_SPREAD_FIXED ? (const void *)k_batch<double, kModeFixed, true, true>
-                                                         : (const void *)k_batch<double, kModeAtomic, true, true>);
-    else
-        kfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? (const void *)k_batch<float, kModeFixed, true, false>
-                                                         : (const void *)k_batch<float, kModeAtomic, true, false>)
-                              : (mode == OT_SPREAD_FIXED ? (const void *)k_batch<double, kModeFixed, true, false>
-                                                         : (const void *)k_batch<double, kModeAtomic, true, false>);
+    p->small_table = tile <= kSmallTile;
+    const void *kfn = dtype == OT_F32
+                          ? (mode == OT_SPREAD_FIXED ? kbatch_fn<float, kModeFixed>(p->grad_plan, p->small_table)
+                                                     : kbatch_fn<float, kModeAtomic>(p->grad_plan, p->small_table))
+                          : (mode == OT_SPREAD_FIXED ? kbatch_fn<double, kModeFixed>(p->grad_plan, p->small_table)
+                                                     : kbatch_fn<double, kModeAtomic>(p->grad_plan, p->small_table));
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, block, 0);
     if (per_cu <= 0) per_cu = 1;
     int grid = tuning && tuning->grid ? tuning->grid : std::max(1, cus) * per_cu;

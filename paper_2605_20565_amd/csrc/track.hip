@@ -45,13 +45,6 @@ __global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t t
 }
 
 constexpr int kMaxPointsPerThread = 4;
-// Tiles of at most kSmallTile points spread through a table of kSmallSlots
-// slots (14 KiB instead of 56 KiB of LDS): such launches are many small
-// workgroups whose time is latency, and the large table would hold the CU
-// to two of them (measured on 11 k points: 76 -> 63 us per fused launch;
-// tiles of 128 bubble markers already reach more leaves than 512 slots).
-constexpr int64_t kSmallTile = 64;
-constexpr int kSmallSlots = 512;
 
 template <typename T, int OPS, int MODE, int S>
 void launch_track(const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStream_t s, int64_t n, const T *P, const T *Fd,

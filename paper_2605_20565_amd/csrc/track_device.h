@@ -490,4 +490,12 @@ __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, i
 template <typename T, int MODE>
 struct SinkSlots { static constexpr int value = 2048; };
 
+// Tiles of at most kSmallTile points spread through a table of kSmallSlots
+// slots (14 KiB instead of 56 KiB of LDS): such launches are many small
+// workgroups whose time is latency, and the large table would hold the CU
+// to two of them (measured on 11 k points: 76 -> 63 us per fused launch;
+// tiles of 128 bubble markers already reach more leaves than 512 slots).
+constexpr int64_t kSmallTile = 64;
+constexpr int kSmallSlots = 512;
+
 }  // namespace ot
