@@ -136,7 +136,7 @@ def test_mdf_touched_leaves_equal_dense_composition(ot, dtype):
     o = oracle_tree(w.tree)
     t = gpu_tree(w.tree)
     u0 = to_dev(as_dtype(o.permute_rows(w.field), dtype), dtype)
-    n_iter, dt, rho = 4, 0.5, 2.0
+    n_iter, dt, rho = 4, 0.5, 2.0   # powers of two: torch's scalar division by reciprocal is exact here
     ug, flg, feg = t.mdf(u0, pos, target, n_iter, dt, rho, mode="fixed")
     u = u0.clone()
     fl = torch.zeros_like(pos)
@@ -161,3 +161,44 @@ def test_mdf_touched_leaves_equal_dense_composition(ot, dtype):
     assert torch.equal(ua, ug)
     uc, _, _ = t.mdf(u0, pos[:100], target[:100], n_iter, dt, rho, mode="fixed")
     assert torch.equal(ub, uc)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_mdf_walled_tree_markers_outside(ot, dtype):
+    """Walled domain with some markers outside the cube: they have no host,
+    interpolate to zero and spread nothing, and the sorted, listed path
+    still equals the dense composition bit for bit (FIXED)."""
+    spec = synth.band_tree(3, 5, [synth.Sphere((0.5, 0.5, 0.5), 0.2)], periodic=False, seed=6)
+    t = gpu_tree(spec)
+    o = oracle_tree(spec)
+    rng = np.random.default_rng(4)
+    inside = synth.fibonacci_sphere(synth.Sphere((0.5, 0.5, 0.5), 0.2), 800, wrap=False)
+    outside = rng.random((50, 3)) + np.array([1.2, 0.0, 0.0])
+    markers = np.concatenate([inside[:400], outside, inside[400:]])
+    pos = to_dev(as_dtype(markers, dtype), dtype)
+    target = to_dev(as_dtype(_rigid_targets(markers, (0.5, 0.5, 0.5)), dtype), dtype)
+    u0 = to_dev(as_dtype(rng.standard_normal((spec.n_leaves, 3)), dtype), dtype)
+    n_iter, dt, rho = 3, 1.0, 1.5
+    ug, flg, feg = t.mdf(u0, pos, target, n_iter, dt, rho, mode="fixed")
+    u = u0.clone()
+    fl = torch.zeros_like(pos)
+    fe = torch.zeros_like(u0)
+    # true divisions by tensors: torch divides by a Python scalar through its
+    # reciprocal, which is not the kernel's arithmetic unless 1/rho is exact
+    dt_t, rho_t = torch.full_like(pos, dt), torch.full_like(u0, rho)
+    for _ in range(n_iter):
+        F = (target - t.interpolate(u, pos)) / dt_t
+        f = t.spread(F, pos, mode="fixed")
+        u = u + f / rho_t
+        fl = fl + F
+        fe = fe + f
+    assert torch.equal(ug, u)
+    assert torch.equal(flg, fl)
+    assert torch.equal(feg, fe)
+    # the outside markers' force is the whole target slip each iteration
+    out = slice(400, 450)
+    assert torch.equal(flg[out], n_iter * (target[out] / dt_t[out]))
+    # and against the oracle composition
+    u_o, _, _ = _ibm().mdf(o, u0.cpu().double().numpy(), pos.cpu().double().numpy(),
+                           target.cpu().double().numpy(), n_iter, dt, rho)
+    assert np.abs(ug.cpu().double().numpy() - u_o).max() <= 10 * TOL[dtype] * (1 + np.abs(u_o).max()) * 10

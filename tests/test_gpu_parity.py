@@ -555,3 +555,30 @@ def test_batch_sorted_points_match_plain(ot, cfg1, cfg1_gpu, dtype, mode):
     with pytest.raises(ot.OtError):
         ot.BatchPlan(cfg1_gpu, off, [7, 3, 7], dtype=dtype, mode=mode, sort_points=True)
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batch_gradient_plan_walled_deep_tree(ot, dtype):
+    """Gradient plans on a walled tree with several table levels (nodes
+    outside the cube dropped, points outside it without a host), sorted:
+    equal to the one-pass entries bit for bit."""
+    spec = synth.band_tree(2, 9, [synth.Sphere((0.3, 0.6, 0.5), 0.2), synth.Sphere((0.8, 0.2, 0.15), 0.1)],
+                           periodic=False, seed=5)
+    t = gpu_tree(spec)
+    rng = np.random.default_rng(12)
+    pts = as_dtype(np.concatenate([synth.fibonacci_sphere(synth.Sphere((0.3, 0.6, 0.5), 0.2), 3000, wrap=False),
+                                   rng.random((3000, 3)), _extra_points(rng, 9, 300)]), dtype)
+    g = as_dtype(rng.standard_normal(pts.shape), dtype)
+    fld = as_dtype(rng.standard_normal((spec.n_leaves, 3)), dtype)
+    P, G, Fd = to_dev(pts, dtype), to_dev(g, dtype), to_dev(fld, dtype)
+    n = P.shape[0]
+    off = [0, 3000, n]
+    plan = ot.BatchPlan(t, off, [ot.OT_OP_SPREAD | ot.OT_OP_GRAD_POS] * 2, dtype=dtype, mode="fixed",
+                        sort_points=True)
+    gf = torch.empty((t.n_leaves, 3), dtype=dtype, device="cuda")
+    gx = torch.empty((n, 3), dtype=dtype, device="cuda")
+    plan.run(P, field=Fd, force=G, field_out=gf, grad=gx)
+    ref_f, ref_x = t.interp_backward(Fd, G, P, mode="fixed")
+    assert torch.equal(gf, ref_f)
+    assert torch.equal(gx, ref_x)
+    plan.close()
