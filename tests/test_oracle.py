@@ -405,3 +405,35 @@ def test_node_leaf_contains_node_centre(orc):
         assert np.all((a <= centre) & (centre < a + size[leaf][:, None])), q
         jumps += int((tree.levels[leaf] != level).sum())
     assert jumps > 1000     # level jumps are exercised
+
+
+# ---------------------------------------------------------------------------
+# Properties over drawn trees (hypothesis): Algorithm 1 equals the linear
+# scan, constants are reproduced, spreading conserves the total force and is
+# the adjoint of interpolation, on any partition the generator can make.
+# ---------------------------------------------------------------------------
+from hypothesis import HealthCheck, given, settings, strategies as st
+
+
+@settings(max_examples=30, deadline=None, suppress_health_check=[HealthCheck.function_scoped_fixture])
+@given(seed=st.integers(0, 2 ** 32 - 1), l_min=st.integers(0, 2), depth=st.integers(1, 3),
+       p_refine=st.floats(0.05, 0.5), periodic=st.booleans(), balance=st.booleans())
+def test_property_drawn_trees(orc, seed, l_min, depth, p_refine, periodic, balance):
+    rng = np.random.default_rng(seed)
+    spec = synth.random_tree(l_min, l_min + depth, rng, p_refine=p_refine, periodic=periodic, balance=balance)
+    tree = _tree(orc, spec)
+    assert tree.check_partition() == 0
+    pts = _adversarial_points(rng, spec, 60)
+    a = tree.locate(pts, "alg1")
+    assert np.array_equal(a, tree.locate(pts, "linear"))
+    if not periodic:
+        return   # walls drop nodes: the sums below hold for periodic cubes
+    c = np.array([0.75, -1.5, 2.0])
+    U = tree.interpolate(np.tile(c, (tree.n_leaves, 1)), pts)
+    np.testing.assert_allclose(U, np.tile(c, (pts.shape[0], 1)), rtol=1e-13, atol=0)
+    F = rng.standard_normal(pts.shape)
+    f = tree.spread(F, pts)
+    np.testing.assert_allclose(f.sum(axis=0), F.sum(axis=0), rtol=1e-12, atol=1e-12 * np.abs(F).sum())
+    u = rng.standard_normal((tree.n_leaves, 3))
+    lhs, rhs = float((f * u).sum()), float((F * tree.interpolate(u, pts)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * (np.abs(f).sum() * np.abs(u).max() + 1.0)
