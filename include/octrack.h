@@ -230,13 +230,16 @@ int ot_spread_backward(const ot_tree *tree, const void *grad_field, const void *
  * of f (the total forcing of the time step).  work: caller-owned device
  * buffer of ot_mdf_workspace_bytes(tree, n, dtype) bytes, 8-byte aligned;
  * the call allocates nothing and enqueues kernels only (no memset), so it
- * can be captured in a graph.  Once per call the markers are sorted by host
- * leaf and the leaves their stencils reach are listed; the iterations run
- * over the sorted markers and clear, convert and update only the listed
- * leaves (results as in input order; FIXED bitwise so).  At most 2^31 - 1
- * markers (OT_ERR_CAPACITY).  Uses the tree's spreading workspace in FIXED mode
- * (calls on one tree must not run concurrently).  Errors: OT_ERR_INVALID
- * (null arrays, n < 0, n_iter < 0, dt or rho not positive, bad mode/dtype,
+ * can be captured in a graph.  Once per call every marker's 27 node leaves
+ * and weights are computed and kept, the leaves they reach listed and the
+ * (marker, node) pairs grouped by leaf; each iteration then gathers through
+ * the kept stencils and sums each listed leaf's pairs (no atomic adds).
+ * Results are those of the plain composition of ot_interpolate and
+ * ot_spread (FIXED: bit for bit; ATOMIC: each leaf's sum in FP64, rounded
+ * once).  The tree is only read: calls on one tree may run concurrently
+ * with their own workspaces.  At most 159,072,862 markers (OT_ERR_CAPACITY).
+ * Errors: OT_ERR_INVALID (null arrays, n < 0, n_iter < 0, dt or rho not
+ * positive, bad mode/dtype,
  * misaligned work), OT_ERR_HIP. */
 int64_t ot_mdf_workspace_bytes(const ot_tree *tree, int64_t n, int32_t dtype);
 

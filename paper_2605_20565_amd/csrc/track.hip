@@ -221,15 +221,6 @@ int run_pass(const ot_tree *t, int ops, const void *field, const void *force, co
 
 }  // namespace
 
-// Spreading kernel alone into fout (ATOMIC) or the fixed-point accumulators
-// (FIXED): the caller has cleared what it reads back and, in FIXED mode,
-// prepared the scale (spread_scale).
-int spread_kernel(const ot_tree *t, int dtype, int mode, const void *force, const void *pos, int64_t n, void *fout,
-                  hipStream_t s)
-{
-    return launch_ops(t, kOpSpread, nullptr, force, pos, dtype, n, mode, nullptr, nullptr, fout, nullptr, s);
-}
-
 int track(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
           int mode, int accumulate, int32_t *ids, void *vel, void *fout, hipStream_t s)
 {

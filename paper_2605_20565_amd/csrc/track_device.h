@@ -448,10 +448,9 @@ __device__ __forceinline__ double bits_value<double>(unsigned long long b) { ret
 // leaf sum stays below 2^62 in magnitude (weights are >= 0 and one point's
 // weights sum to 1) and every single contribution below 2^51.
 template <typename T>
-__global__ void k_fx_prepare(FxState *fx, int64_t n)
+__device__ __forceinline__ int fx_shift(unsigned long long maxbits, int64_t n)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double mf = bits_value<T>(fx->maxbits);
+    const double mf = bits_value<T>(maxbits);
     int s = 0;
     if (mf > 0.0 && n > 0) {
         int E, Ef;
@@ -459,6 +458,14 @@ __global__ void k_fx_prepare(FxState *fx, int64_t n)
         (void)frexp(mf, &Ef);
         s = min(62 - E, 51 - Ef);
     }
+    return s;
+}
+
+template <typename T>
+__global__ void k_fx_prepare(FxState *fx, int64_t n)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int s = fx_shift<T>(fx->maxbits, n);
     fx->scale = ldexp(1.0, s);
     fx->inv = ldexp(1.0, -s);
 }
