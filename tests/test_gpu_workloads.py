@@ -272,6 +272,61 @@ def test_cfg5_autograd_against_oracle(ot, cfg2):
                          fixed_point_quantum(g)) <= 1.0
 
 
+def test_cfg5_batched_gradient_plan_equals_one_pass(ot):
+    """Workload 5 at full size (10^6 markers, 125 k per bubble): the sorted
+    batched backward of interpolation equals the plain one-pass entry bit
+    for bit (FIXED), in the launch shape the bench's plan uses."""
+    _say("generating workload 5 (batched gradient)")
+    w5 = synth.workload(5)
+    dt = torch.float32
+    t = gpu_tree(w5.tree)
+    P = to_dev(as_dtype(w5.points, dt), dt)
+    rng = np.random.default_rng(56)
+    G = to_dev(as_dtype(rng.standard_normal(w5.points.shape), dt), dt)
+    u = t.permute_rows(to_dev(as_dtype(w5.field, dt), dt))
+    ref_f, ref_x = t.interp_backward(u, G, P, mode="fixed")
+    plan = ot.BatchPlan(t, [0, P.shape[0]], [ot.OT_OP_SPREAD | ot.OT_OP_GRAD_POS], dtype=dt, mode="fixed",
+                        sort_points=True)
+    gf = torch.empty_like(u)
+    gx = torch.empty_like(P)
+    plan.run(P, field=u, force=G, field_out=gf, grad=gx)
+    torch.cuda.synchronize()
+    assert torch.equal(gf, ref_f)
+    assert torch.equal(gx, ref_x)
+    plan.close()
+
+
+def test_cfg2_mdf_markers_equal_dense_composition(ot, cfg2):
+    """Multi-direct forcing on workload 2's 65,880 bubble markers (2.66 M
+    leaves): the kept stencils and per-leaf pair sums give, bit for bit, the
+    dense composition of the library's interpolation and spreading (FIXED),
+    with the elementwise steps as true divisions."""
+    w, o = cfg2
+    dt_ = torch.float32
+    t = gpu_tree(w.tree)
+    idx = [i for i, k in enumerate(w.kinds) if k == "markers"]
+    sel = np.concatenate([np.arange(w.instances[i], w.instances[i + 1]) for i in idx])
+    P = to_dev(as_dtype(w.points[sel], dt_), dt_)
+    rng = np.random.default_rng(21)
+    target = to_dev(as_dtype(0.1 * rng.standard_normal(P.shape), dt_), dt_)
+    u0 = t.permute_rows(to_dev(as_dtype(w.field, dt_), dt_))
+    n_iter, step, rho = 3, 0.75, 1.25
+    ug, flg, feg = t.mdf(u0, P, target, n_iter, step, rho, mode="fixed")
+    u = u0.clone()
+    step_t, rho_t = torch.full_like(P, step), torch.full_like(u0, rho)
+    fl = torch.zeros_like(P)
+    fe = torch.zeros_like(u0)
+    for _ in range(n_iter):
+        F = (target - t.interpolate(u, P)) / step_t
+        f = t.spread(F, P, mode="fixed")
+        u = u + f / rho_t
+        fl = fl + F
+        fe = fe + f
+    assert torch.equal(ug, u)
+    assert torch.equal(flg, fl)
+    assert torch.equal(feg, fe)
+
+
 def test_autograd_matches_central_differences_fp64(ot):
     """FP64 gradients of the pair against central differences with
     h = 1e-4 finest dx, points kept away from cell faces and phi kinks."""
