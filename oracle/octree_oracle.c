@@ -34,6 +34,10 @@
  *     stencil node (a level-l cell) is read from the leaf that contains the
  *     node's centre (half-open rule, so a centre on a corner of finer cells
  *     belongs to the upper child);
+ *     PARITY UNPINNED for stencils that cross a level jump: the paper gives
+ *     no value there.  The tests pin this reading's implementation by
+ *     geometry (the node's leaf contains its centre) and by self-consistency
+ *     (conservation, the adjoint identity, constants reproduced);
  *   - spread is the exact transpose of interpolate: both use the weights
  *     phi(rx) phi(ry) phi(rz) without a cell-volume factor (the (dx)^D of the
  *     sums cancels the 1/dx^D of W);

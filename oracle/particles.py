@@ -6,8 +6,10 @@ Plain FP64 per particle, in this order:
    nodes are the level-l cells i0, i0 + 1 per axis around s = x 2^l - 1/2
    (i0 = floor(s), weights 1 - t and t, t = s - i0); each node's value is read
    from the leaf that contains the node's centre (the same reading as the
-   delta-function stencil); periodic wrap, or nodes outside a walled domain
-   dropped with their weight;
+   delta-function stencil; parity unpinned where the 8 nodes cross a level
+   jump, which the paper does not spell out: the pins hold constants on
+   adaptive trees and linear fields on uniform ones); periodic wrap, or
+   nodes outside a walled domain dropped with their weight;
 3. particle Reynolds number Re = 2 r_p |u - v| / nu, drag correction
    f = 1 + 0.15 Re^0.687, acceleration
    a = f (u - v) / tau + (1 - rho_f / rho_p) g,  tau = 2 rho_p r_p^2 / (9 rho_f nu)
