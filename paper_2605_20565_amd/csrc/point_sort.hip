@@ -11,8 +11,8 @@
 //
 // A pass takes tiles of 2048 points: the keys are staged in LDS with
 // coalesced loads, ranked stably by the digit with eight 1-bit splits, and
-// every digit's run is written contiguously; the record of a point is
-// gathered from inside the tile and written once.  (Tiles of 4096 and 8192
+// every digit's run is written contiguously; the records, read once in
+// input order, move to their sorted slots through LDS in small chunks.  (Tiles of 4096 and 8192
 // points give longer runs but fewer workgroups in flight, and were slower.)  The
 // first pass's digit counts come from the key kernel, and the first pass also
 // takes max |F| for the fixed-point scale, since it reads every force anyway.
@@ -31,6 +31,25 @@ constexpr int kTile = kThreads * kItems;   // 2048
 constexpr int kBits = 8;
 constexpr int kBuckets = 1 << kBits;
 static_assert(kThreads == kBuckets, "one digit per thread in the digit scan");
+
+// CW consecutive record values as one LDS word of the staging buffer.
+template <typename T, int CW>
+struct Chunk2;
+template <>
+struct Chunk2<float, 2> {
+    using type = float2;
+    static __device__ __forceinline__ float2 pack(const float *v, int c) { return make_float2(v[c], v[c + 1]); }
+};
+template <>
+struct Chunk2<double, 2> {
+    using type = double2;
+    static __device__ __forceinline__ double2 pack(const double *v, int c) { return make_double2(v[c], v[c + 1]); }
+};
+template <typename T>
+struct Chunk2<T, 1> {
+    using type = T;
+    static __device__ __forceinline__ T pack(const T *v, int c) { return v[c]; }
+};
 
 // LDS index with one pad word per 32: the blocked reads (stride kItems) and
 // the striped writes both spread over the banks.
@@ -205,35 +224,78 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         dstart[threadIdx.x] = exscan_256(c, sh_w, tot);
     }
     __syncthreads();
-    // coalesced writes: sorted position i goes to its digit's run; the record
-    // is gathered from inside the tile
+    // Records are read once, in input order (coalesced), into registers and
+    // reach their sorted positions through LDS in chunks of CW values (the
+    // whole tile's records at once would take too much LDS: fewer
+    // workgroups in flight); words and records are then written in sorted
+    // order, contiguously within each digit's run.  (Gathering each record
+    // from global memory instead, at its source inside the tile, fetched
+    // about 4x its bytes past L2 and took 319 against 232 us per pass on
+    // 10^7 points.)
+    constexpr int CW = (R % 2 == 0) ? 2 : 1;
+    using Chunk = typename Chunk2<T, CW>::type;
+    __shared__ Chunk stg[kPadded];
+    __shared__ uint32_t slo[kPadded];
+    T rv[kItems][R];
+    uint32_t lo[kItems];
     unsigned long long mx = 0;
+#pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        const int i = j * kThreads + threadIdx.x;
-        if (i < valid) {
-            const uint32_t key = sk[pad(i)];
-            const int64_t src = base + si[pad(i)];
-            const uint32_t d = (key >> shift) & (kBuckets - 1);
-            const int64_t dst = (int64_t)offs[(int64_t)d * nblocks + tile] + (i - (int)dstart[d]);
-            kout[dst] = ((uint64_t)key << 32) | (uint32_t)kin[src];
-            T v[R];
+        const int li = j * kThreads + threadIdx.x;
+        lo[j] = 0u;
+#pragma unroll
+        for (int c = 0; c < R; ++c) rv[j][c] = T(0);
+        if (li < valid) {
+            const int64_t src = base + li;
+            lo[j] = (uint32_t)kin[src];
             if (rin) {
 #pragma unroll
-                for (int c = 0; c < R; ++c) v[c] = rin[R * src + c];
+                for (int c = 0; c < R; ++c) rv[j][c] = rin[R * src + c];
             } else {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) v[c] = pos[3 * src + c];
+                for (int c = 0; c < 3; ++c) rv[j][c] = pos[3 * src + c];
 #pragma unroll
-                for (int c = 3; c < R; ++c) v[c] = force[3 * src + (c - 3)];
+                for (int c = 3; c < R; ++c) rv[j][c] = force[3 * src + (c - 3)];
             }
-#pragma unroll
-            for (int c = 0; c < R; ++c) rout[R * dst + c] = v[c];
             if (maxbits) {
 #pragma unroll
                 for (int c = 3; c < R; ++c)
-                    if (isfinite(v[c])) mx = std::max(mx, abs_bits_of(v[c]));
+                    if (isfinite(rv[j][c])) mx = std::max(mx, abs_bits_of(rv[j][c]));
             }
         }
+    }
+    // sorted position i = j * kThreads + thread: its destination and source slot
+    int64_t dstv[kItems];
+    int srcv[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int i = j * kThreads + threadIdx.x;
+        dstv[j] = -1;
+        srcv[j] = 0;
+        if (i < valid) {
+            const uint32_t key = sk[pad(i)];
+            const uint32_t d = (key >> shift) & (kBuckets - 1);
+            dstv[j] = (int64_t)offs[(int64_t)d * nblocks + tile] + (i - (int)dstart[d]);
+            srcv[j] = si[pad(i)];
+        }
+    }
+#pragma unroll
+    for (int ch = 0; ch < R / CW; ++ch) {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int li = j * kThreads + threadIdx.x;
+            stg[pad(li)] = Chunk2<T, CW>::pack(rv[j], CW * ch);
+            if (ch == 0) slo[pad(li)] = lo[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            if (dstv[j] < 0) continue;
+            const int i = j * kThreads + threadIdx.x;
+            if (ch == 0) kout[dstv[j]] = ((uint64_t)sk[pad(i)] << 32) | slo[pad(srcv[j])];
+            reinterpret_cast<Chunk *>(rout)[(R * dstv[j]) / CW + ch] = stg[pad(srcv[j])];
+        }
+        __syncthreads();
     }
     if (maxbits) block_max_to(mx, sh_max, maxbits);
 }
