@@ -44,7 +44,7 @@ struct ot_batch_plan {
     int ops_all;              // the common ops of every instance
     bool grad_plan;           // instances carry OT_OP_GRAD_POS
     bool small_table;         // tiles of at most kSmallTile points: the small spreading table
-    uint64_t *skv[2];         // host << 32 | input index, in sorted order
+    uint64_t *skv[2];         // host's leaf entry << 32 | input index, in sorted order
     void *srec[2];            // position (+ force) records in sorted order
     void *sws;                // counting workspace
 };

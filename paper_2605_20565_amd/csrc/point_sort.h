@@ -14,14 +14,14 @@ namespace ot {
 // pass, set 0 after the second), plus the counting workspace.
 template <typename T>
 struct PointSortBufs {
-    uint64_t *kv[2];   // n words: host << 32 | input index
+    uint64_t *kv[2];   // n words: host's leaf entry << 32 | input index
     T *rec[2];         // n records of 6 (position, force) or 3 (position) values
     void *ws;          // point_sort_ws_bytes(n)
 };
 
 template <typename T>
 struct PointSortResult {
-    const uint64_t *kv;   // per sorted position: host << 32 | input index
+    const uint64_t *kv;   // per sorted position: host's leaf entry << 32 | input index
     const T *rec;         // per sorted position: stride values, position first
     int stride;           // 6 with forces, 3 without
 };
@@ -42,9 +42,9 @@ inline void point_sort_key_bits(int64_t n_leaves, int &shift, int &bits)
     bits = all - shift;
 }
 
-// Keys (host leaf ids; points without a host get n_leaves), ids when
-// ids != null, then ceil(bits / 8) stable passes over key bits
-// [shift, shift + bits); bits >= 1.  force != null: records carry forces
+// Keys (the host's leaf entry, id in the low 26 bits; points without a
+// host get n_leaves), ids when ids != null, then ceil(bits / 8) stable
+// passes over id bits [shift, shift + bits); bits >= 1.  force != null: records carry forces
 // too, and when maxbits != null the first pass also atomically maxes the
 // bit pattern of max |F| (finite components) into *maxbits.
 template <typename T>

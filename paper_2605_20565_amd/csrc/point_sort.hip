@@ -4,7 +4,7 @@
 // Neighbouring threads of the tracking pass then work on neighbouring host
 // cells: their stencil nodes share cache lines and the workgroup's spreading
 // table, and positions and forces are read with coalesced loads.  Each point
-// is one 64-bit word host << 32 | input index plus one record of R values
+// is one 64-bit word (host's leaf entry) << 32 | input index plus one record of R values
 // (position, then force when spreading).  The passes order by key bits
 // [shift, shift + bits) only (groups of 2^shift consecutive leaves; 8-bit
 // LSD passes, see point_sort_key_bits).
@@ -101,8 +101,9 @@ __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long
     }
 }
 
-// Host leaf of every point (and ids when asked): kv = host << 32 | index,
-// points without a host get host = n_leaves.  Workgroup b covers the first
+// Host leaf of every point (and ids when asked): kv = entry << 32 | index
+// with the host's leaf entry (level << 26 | id); points without a host get
+// n_leaves.  Digits are taken from the id bits only.  Workgroup b covers the first
 // pass's tile b and leaves its digit counts in counts[d * nblocks + b].
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n, const T *__restrict__ pos,
@@ -120,10 +121,12 @@ __global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n,
         if (k < n) {
             uint32_t I[3];
             const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
-            const uint32_t host = ok ? (descend(tv, I[0], I[1], I[2]) & kIdMask) : none;
-            if (ids) ids[k] = ok ? (int32_t)host : -1;
-            kv[k] = ((uint64_t)host << 32) | (uint32_t)k;
-            atomicAdd(&hist[(host >> shift) & (kBuckets - 1)], 1u);
+            // the host's whole leaf entry (level << 26 | id): the tracking pass
+            // takes it from here instead of searching again
+            const uint32_t e = ok ? descend(tv, I[0], I[1], I[2]) : none;
+            if (ids) ids[k] = ok ? (int32_t)(e & kIdMask) : -1;
+            kv[k] = ((uint64_t)e << 32) | (uint32_t)k;
+            atomicAdd(&hist[((e & kIdMask) >> shift) & (kBuckets - 1)], 1u);
         }
     }
     __syncthreads();
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_point_hist(const uint64_t *__restr
     const int64_t base = (int64_t)blockIdx.x * kTile;
     for (int j = threadIdx.x; j < kTile; j += kThreads) {
         const int64_t i = base + j;
-        if (i < n) atomicAdd(&hist[(uint32_t)(kv[i] >> (32 + shift)) & (kBuckets - 1)], 1u);
+        if (i < n) atomicAdd(&hist[(((uint32_t)(kv[i] >> 32) & kIdMask) >> shift) & (kBuckets - 1)], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + blockIdx.x] = hist[d];
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         uint32_t key = 0xFFFFFFFFu;
         if (li < valid) {
             key = (uint32_t)(kin[base + li] >> 32);
-            atomicAdd(&dcount[(key >> shift) & (kBuckets - 1)], 1u);
+            atomicAdd(&dcount[((key & kIdMask) >> shift) & (kBuckets - 1)], 1u);
         }
         sk[pad(li)] = key;
         si[pad(li)] = (uint16_t)li;
@@ -196,12 +199,12 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     for (int b = 0; b < kBits; ++b) {
         uint32_t zeros = 0;
 #pragma unroll
-        for (int j = 0; j < kItems; ++j) zeros += 1u - ((k[j] >> (shift + b)) & 1u);
+        for (int j = 0; j < kItems; ++j) zeros += 1u - (((k[j] & kIdMask) >> (shift + b)) & 1u);
         uint32_t total_zeros;
         uint32_t zb = exscan_256(zeros, sh_w, total_zeros);
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
-            const uint32_t bit = (k[j] >> (shift + b)) & 1u;
+            const uint32_t bit = ((k[j] & kIdMask) >> (shift + b)) & 1u;
             const uint32_t g = (uint32_t)(t0 + j);
             const uint32_t p = bit ? total_zeros + (g - zb) : zb;
             zb += 1u - bit;
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         srcv[j] = 0;
         if (i < valid) {
             const uint32_t key = sk[pad(i)];
-            const uint32_t d = (key >> shift) & (kBuckets - 1);
+            const uint32_t d = ((key & kIdMask) >> shift) & (kBuckets - 1);
             dstv[j] = (int64_t)offs[(int64_t)d * nblocks + tile] + (i - (int)dstart[d]);
             srcv[j] = si[pad(i)];
         }

@@ -282,21 +282,24 @@ struct LdsSink {
 
 // Point k: position pos[rs k + 0..2], force force[rs k + 0..2] (rs = 3 for
 // the caller's arrays, the record stride for sorted records).  With kv
-// (sorted points: host << 32 | input index) the per-point outputs go to the
-// input index.  With kOpGrad, force[k] is also the vector the gradient
-// contracts the field with, and the gradient goes to grad.
+// (sorted points: the host's leaf entry << 32 | input index) the host comes
+// from the word, found by the sort's key pass on the same position, and the
+// per-point outputs go to the input index.  With kOpGrad, force[k] is also
+// the vector the gradient contracts the field with, and the gradient goes
+// to grad.
 template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const uint64_t *__restrict__ kv, int rs,
                                             const T *__restrict__ pos, const T *__restrict__ field,
                                             const T *__restrict__ force, int32_t *__restrict__ ids,
                                             T *__restrict__ vel, Sink &sink, T *__restrict__ grad = nullptr)
 {
-    const int64_t kd = kv ? (int64_t)(uint32_t)kv[k] : k;
+    const uint64_t word = kv ? kv[k] : 0ull;
+    const int64_t kd = kv ? (int64_t)(uint32_t)word : k;
     const int64_t kp = (int64_t)rs * k;
     const T X[3] = {pos[kp], pos[kp + 1], pos[kp + 2]};
     uint32_t I[3];
     const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
-    const uint32_t e = ok ? descend(tv, I[0], I[1], I[2]) : 0u;
+    const uint32_t e = ok ? (kv ? (uint32_t)(word >> 32) : descend(tv, I[0], I[1], I[2])) : 0u;
     if (OPS & kOpLocate) ids[kd] = ok ? (int32_t)(e & kIdMask) : -1;
     if (!(OPS & (kOpInterp | kOpSpread | kOpGrad))) return;
 
