@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ot_common.h"
+#include "track_device.h"
 
 namespace ot {
 namespace {
@@ -44,10 +45,17 @@ __global__ __launch_bounds__(256) void k_particle_step(TreeView tv, int l_min, i
             i0[d] = (int64_t)f;
             t[d] = (T)(s - f);
         }
+        // the 8 nodes: root-table entries issued together, the deeper descent
+        // only under split root cells, then the gathers (independent loads
+        // instead of one search after another)
+        uint32_t nc[8][3];
+        uint32_t ent[8];
+        T wq[8];
+        uint32_t inside = 0u;
+        const int rsh = tv.L - tv.lev[0];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int o[3] = {q & 1, (q >> 1) & 1, (q >> 2) & 1};
-            uint32_t nc[3];
             bool in = true;
             T w = T(1);
 #pragma unroll
@@ -55,14 +63,24 @@ __global__ __launch_bounds__(256) void k_particle_step(TreeView tv, int l_min, i
                 int64_t c = i0[d] + o[d];
                 if (PER) c &= (M - 1);
                 else in = in && c >= 0 && c < M;
-                nc[d] = (uint32_t)(((c < 0 ? 0 : c) << sh) | half);
+                nc[q][d] = (uint32_t)(((c < 0 ? 0 : c) << sh) | half);
                 w *= o[d] ? t[d] : T(1) - t[d];
             }
-            if (!in) continue;   // node outside the walls: dropped with its weight
-            const int64_t j = 3 * (int64_t)(descend(tv, nc[0], nc[1], nc[2]) & kIdMask);
-            U[0] = fma(w, field[j], U[0]);
-            U[1] = fma(w, field[j + 1], U[1]);
-            U[2] = fma(w, field[j + 2], U[2]);
+            wq[q] = w;
+            inside |= (in ? 1u : 0u) << q;
+            // a node outside the walls is dropped with its weight
+            ent[q] = in ? ld_table(tv, interleave3(nc[q][0] >> rsh, nc[q][1] >> rsh, nc[q][2] >> rsh)) : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (ent[q] & kSplit) ent[q] = descend_below_root(tv, ent[q], nc[q][0], nc[q][1], nc[q][2]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (!((inside >> q) & 1u)) continue;
+            const int64_t j = 3 * (int64_t)(ent[q] & kIdMask);
+            U[0] = fma(wq[q], field[j], U[0]);
+            U[1] = fma(wq[q], field[j + 1], U[1]);
+            U[2] = fma(wq[q], field[j + 2], U[2]);
         }
         dt = ldexp(p.dt0, -(l - l_min));
     }
