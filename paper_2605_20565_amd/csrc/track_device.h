@@ -280,26 +280,25 @@ struct LdsSink {
     }
 };
 
-// Point k: position pos[rs k + 0..2], force force[rs k + 0..2] (rs = 3 for
-// the caller's arrays, the record stride for sorted records).  With kv
-// (sorted points: the host's leaf entry << 32 | input index) the host comes
-// from the word, found by the sort's key pass on the same position, and the
-// per-point outputs go to the input index.  With kOpGrad, force[k] is also
+// Point k: position X (loaded by the caller from pos[rs k + 0..2]), force
+// force[rs k + 0..2] (rs = 3 for the caller's arrays, the record stride for
+// sorted records).  For sorted points, word is the point's sort word (the
+// host's leaf entry << 32 | input index): the host comes from the word,
+// found by the sort's key pass on the same position, and the per-point
+// outputs go to the input index.  With kOpGrad, force[k] is also
 // the vector the gradient contracts the field with, and the gradient goes
 // to grad.
 template <typename T, int OPS, bool PER, typename Sink>
-__device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const uint64_t *__restrict__ kv, int rs,
-                                            const T *__restrict__ pos, const T *__restrict__ field,
-                                            const T *__restrict__ force, int32_t *__restrict__ ids,
-                                            T *__restrict__ vel, Sink &sink, T *__restrict__ grad = nullptr)
+__device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bool sorted, uint64_t word,
+                                               const T (&X)[3], int rs, const T *__restrict__ field,
+                                               const T *__restrict__ force, int32_t *__restrict__ ids,
+                                               T *__restrict__ vel, Sink &sink, T *__restrict__ grad)
 {
-    const uint64_t word = kv ? kv[k] : 0ull;
-    const int64_t kd = kv ? (int64_t)(uint32_t)word : k;
+    const int64_t kd = sorted ? (int64_t)(uint32_t)word : k;
     const int64_t kp = (int64_t)rs * k;
-    const T X[3] = {pos[kp], pos[kp + 1], pos[kp + 2]};
     uint32_t I[3];
     const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
-    const uint32_t e = ok ? (kv ? (uint32_t)(word >> 32) : descend(tv, I[0], I[1], I[2])) : 0u;
+    const uint32_t e = ok ? (sorted ? (uint32_t)(word >> 32) : descend(tv, I[0], I[1], I[2])) : 0u;
     if (OPS & kOpLocate) ids[kd] = ok ? (int32_t)(e & kIdMask) : -1;
     if (!(OPS & (kOpInterp | kOpSpread | kOpGrad))) return;
 
@@ -484,6 +483,19 @@ __global__ void k_fx_finalize(const unsigned long long *__restrict__ acc, T *__r
     }
 }
 
+// Point k, loading its sort word (kv non-null) and position first.
+template <typename T, int OPS, bool PER, typename Sink>
+__device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const uint64_t *__restrict__ kv, int rs,
+                                            const T *__restrict__ pos, const T *__restrict__ field,
+                                            const T *__restrict__ force, int32_t *__restrict__ ids,
+                                            T *__restrict__ vel, Sink &sink, T *__restrict__ grad = nullptr)
+{
+    const uint64_t word = kv ? kv[k] : 0ull;
+    const int64_t kp = (int64_t)rs * k;
+    const T X[3] = {pos[kp], pos[kp + 1], pos[kp + 2]};
+    track_point_at<T, OPS, PER, Sink>(tv, k, kv != nullptr, word, X, rs, field, force, ids, vel, sink, grad);
+}
+
 // Process points [start, end) of one tile with all threads of the workgroup.
 template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, int64_t end,
@@ -492,8 +504,36 @@ __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, i
                                             int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink,
                                             T *__restrict__ grad = nullptr)
 {
-    for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x)
-        track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink, grad);
+    if (!kv) {
+        for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x)
+            track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink, grad);
+        return;
+    }
+    // sorted records: the next point's word and position are loaded before
+    // this point's work, so they arrive while it runs
+    int64_t k = start + threadIdx.x;
+    if (k >= end) return;
+    uint64_t w = kv[k];
+    T X[3] = {pos[(int64_t)rs * k], pos[(int64_t)rs * k + 1], pos[(int64_t)rs * k + 2]};
+    for (;;) {
+        const int64_t kn = k + blockDim.x;
+        const bool more = kn < end;
+        uint64_t wn = 0ull;
+        T Xn[3] = {T(0), T(0), T(0)};
+        if (more) {
+            wn = kv[kn];
+            Xn[0] = pos[(int64_t)rs * kn];
+            Xn[1] = pos[(int64_t)rs * kn + 1];
+            Xn[2] = pos[(int64_t)rs * kn + 2];
+        }
+        track_point_at<T, OPS, PER, Sink>(tv, k, true, w, X, rs, field, force, ids, vel, sink, grad);
+        if (!more) break;
+        k = kn;
+        w = wn;
+        X[0] = Xn[0];
+        X[1] = Xn[1];
+        X[2] = Xn[2];
+    }
 }
 
 // LDS table size of the aggregating sink (every slot holds 3 x 8 bytes).
