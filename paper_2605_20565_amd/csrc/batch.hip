@@ -74,11 +74,15 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
     const double scale = MODE == kModeFixed ? fx->scale : 0.0;
     LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
     sink.clear();
+    // The next tile is claimed before the flush, so the queue atomic's round
+    // trip overlaps it.  Every thread reads s_tile before the flush's first
+    // barrier, and thread 0 writes it again only after the flush's last one.
+    unsigned nxt = 0u;
+    if (threadIdx.x == 0) nxt = atomicAdd(counter, 1u);
     for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) s_tile = nxt;
         __syncthreads();
         const int64_t tile = s_tile;
-        __syncthreads();
         if (tile >= n_tiles) break;   // same value in every thread of the workgroup
         const int64_t start = tile_start[tile];
         const uint32_t info = tile_info[tile];
@@ -100,6 +104,7 @@ __global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__res
             default: break;
             }
         }
+        if (threadIdx.x == 0) nxt = atomicAdd(counter, 1u);
         sink.flush();   // one spatially coherent tile per table fill
     }
 }
