@@ -22,11 +22,11 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle into ``liboracle.so`` with gcc (OpenMP, -O2)."""
+    """Compile the oracle into ``liboracle.so`` with gcc (OpenMP, -O2, libquadmath)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lquadmath", "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

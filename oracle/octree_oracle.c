@@ -48,6 +48,7 @@
  * (stencil z outer, y, x inner; points in ascending index order).
  */
 #include <math.h>
+#include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -236,27 +237,38 @@ void orc_locate(const orc_tree *t, const double *pos, int64_t n, int32_t method,
 
 /* ---------------------------------------------------------------------------
  * 3-point discrete delta function phi (Sec. 2.2), on the dimensionless
- * distance r, and its derivative.
+ * distance r, and its derivative, each branch as printed.
+ *
+ * They are evaluated in binary128 (__float128) and rounded once to FP64.
+ * Near the edge of the support (|r| -> 3/2) the outer branch is a difference
+ * of two terms close to 1/2 whose result goes to zero quadratically, so the
+ * printed formula evaluated in FP64 is good only to about 2^-53 absolute;
+ * in binary128 the same formula, in the same order, is good to about 2^-113
+ * absolute, far below any FP64 result it is compared with.
  * ------------------------------------------------------------------------- */
-double orc_phi(double r)
+static __float128 phi_q(__float128 r)
 {
-    double a = fabs(r);
-    if (a <= 0.5) return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
-    if (a <= 1.5) return (5.0 - 3.0 * a - sqrt(-2.0 + 6.0 * a - 3.0 * r * r)) / 6.0;
-    return 0.0;
+    __float128 a = r < 0 ? -r : r;
+    if (a <= 0.5Q) return (1.0Q + sqrtq(1.0Q - 3.0Q * r * r)) / 3.0Q;
+    if (a <= 1.5Q) return (5.0Q - 3.0Q * a - sqrtq(-2.0Q + 6.0Q * a - 3.0Q * r * r)) / 6.0Q;
+    return 0.0Q;
 }
 
-double orc_dphi(double r)
+static __float128 dphi_q(__float128 r)
 {
-    double a = fabs(r);
-    double sg = r < 0.0 ? -1.0 : 1.0;
-    if (a <= 0.5) return -r / sqrt(1.0 - 3.0 * r * r);
-    if (a < 1.5) {
-        double g = -2.0 + 6.0 * a - 3.0 * r * r;
-        return sg * (-3.0 - (6.0 - 6.0 * a) / (2.0 * sqrt(g))) / 6.0;
+    __float128 a = r < 0 ? -r : r;
+    __float128 sg = r < 0 ? -1.0Q : 1.0Q;
+    if (a <= 0.5Q) return -r / sqrtq(1.0Q - 3.0Q * r * r);
+    if (a < 1.5Q) {
+        __float128 g = -2.0Q + 6.0Q * a - 3.0Q * r * r;
+        return sg * (-3.0Q - (6.0Q - 6.0Q * a) / (2.0Q * sqrtq(g))) / 6.0Q;
     }
-    return 0.0;
+    return 0.0Q;
 }
+
+double orc_phi(double r) { return (double)phi_q((__float128)r); }
+
+double orc_dphi(double r) { return (double)dphi_q((__float128)r); }
 
 /* Neumaier-compensated accumulation. */
 static inline void nsum(double *s, double *c, double v)
@@ -267,18 +279,22 @@ static inline void nsum(double *s, double *c, double v)
 }
 
 /* The stencil of one point: host leaf, its level l, per-axis node cell
- * indices at level l (n[d][o], o = 0,1,2 for offsets -1,0,+1), whether each
- * node exists, per-axis 1-D distances r[d][o] = t_d - 1/2 - (o-1), and the
- * leaf holding each of the 27 nodes. */
+ * indices at level l (o = 0,1,2 for offsets -1,0,+1), whether each node
+ * exists, the per-axis 1-D weights ph[d][o] = phi(r) of the distances
+ * r = t_d - 1/2 - (o-1) (and phi'(r) in dph when asked), and the leaf
+ * holding each of the 27 nodes.  The distance is formed in binary128 from
+ * the exact FP64 offset t_d, so it is exact, and phi / phi' are evaluated
+ * there and rounded once. */
 typedef struct {
     int64_t host;
     int level;
-    double r[3][3];
+    double ph[3][3];
+    double dph[3][3];
     int valid[3][3];
     int64_t leaf[27];   /* index oz*9 + oy*3 + ox */
 } stencil;
 
-static int build_stencil(const orc_tree *t, const double x[3], stencil *st)
+static int build_stencil(const orc_tree *t, const double x[3], stencil *st, int want_grad)
 {
     int64_t I[3];
     st->host = -1;
@@ -296,7 +312,9 @@ static int build_stencil(const orc_tree *t, const double x[3], stencil *st)
         double frac = s - floor(s);          /* offset inside the host cell   */
         int64_t i0 = I[d] >> sh;             /* host cell index at level l    */
         for (int o = 0; o < 3; ++o) {
-            st->r[d][o] = frac - 0.5 - (double)(o - 1);
+            __float128 r = (__float128)frac - 0.5Q - (__float128)(o - 1);
+            st->ph[d][o] = (double)phi_q(r);
+            st->dph[d][o] = want_grad ? (double)dphi_q(r) : 0.0;
             int64_t nd = i0 + (o - 1);
             int ok = 1;
             if (t->periodic) { nd %= Ml; if (nd < 0) nd += Ml; }
@@ -335,13 +353,13 @@ void orc_interpolate(const orc_tree *t, const double *field, const double *pos, 
     for (int64_t k = 0; k < n; ++k) {
         stencil st;
         double s[3] = {0, 0, 0}, c[3] = {0, 0, 0}, m[3] = {0, 0, 0};
-        if (build_stencil(t, pos + 3 * k, &st)) {
+        if (build_stencil(t, pos + 3 * k, &st, 0)) {
             for (int oz = 0; oz < 3; ++oz)
                 for (int oy = 0; oy < 3; ++oy)
                     for (int ox = 0; ox < 3; ++ox) {
                         int q = oz * 9 + oy * 3 + ox;
                         if (st.leaf[q] < 0) continue;
-                        double w = orc_phi(st.r[0][ox]) * orc_phi(st.r[1][oy]) * orc_phi(st.r[2][oz]);
+                        double w = st.ph[0][ox] * st.ph[1][oy] * st.ph[2][oz];
                         const double *u = field + 3 * st.leaf[q];
                         for (int e = 0; e < 3; ++e) {
                             nsum(&s[e], &c[e], w * u[e]);
@@ -360,38 +378,81 @@ void orc_interpolate(const orc_tree *t, const double *field, const double *pos, 
  * Spreading (Sec. 2.2):  f(x_n) = sum_k F_k W(x_n - X_k) (dx)^3, the exact
  * transpose of orc_interpolate.  f, scale: (n_leaves, 3); count: contributions
  * per leaf; fabs_sum: sum of |F_k,c| over the contributions (weight-free).
- * The last three are nullable diagnostics.  f is overwritten.  Serial,
- * points in ascending order.
+ * The last three are nullable diagnostics.  f is overwritten.
+ *
+ * The points are cut into one contiguous block per thread (ascending index
+ * order inside each block); every thread sums its block into a private,
+ * compensated copy of the field, and the copies are then added leaf by leaf
+ * in thread order with the same compensation.
  * ------------------------------------------------------------------------- */
 void orc_spread(const orc_tree *t, const double *F, const double *pos, int64_t n,
                 double *f, double *scale, int64_t *count, double *fabs_sum)
 {
-    int64_t nl = t->n_leaves;
-    double *comp = (double *)calloc((size_t)(3 * nl), sizeof(double));
-    memset(f, 0, sizeof(double) * 3 * (size_t)nl);
-    if (scale) memset(scale, 0, sizeof(double) * 3 * (size_t)nl);
-    if (count) memset(count, 0, sizeof(int64_t) * (size_t)nl);
-    if (fabs_sum) memset(fabs_sum, 0, sizeof(double) * 3 * (size_t)nl);
-    for (int64_t k = 0; k < n; ++k) {
-        stencil st;
-        if (!build_stencil(t, pos + 3 * k, &st)) continue;
-        for (int oz = 0; oz < 3; ++oz)
-            for (int oy = 0; oy < 3; ++oy)
-                for (int ox = 0; ox < 3; ++ox) {
-                    int q = oz * 9 + oy * 3 + ox;
-                    int64_t j = st.leaf[q];
-                    if (j < 0) continue;
-                    double w = orc_phi(st.r[0][ox]) * orc_phi(st.r[1][oy]) * orc_phi(st.r[2][oz]);
-                    for (int e = 0; e < 3; ++e) {
-                        nsum(&f[3 * j + e], &comp[3 * j + e], w * F[3 * k + e]);
-                        if (scale) scale[3 * j + e] += fabs(w * F[3 * k + e]);
-                        if (fabs_sum) fabs_sum[3 * j + e] += fabs(F[3 * k + e]);
+    const int64_t nl = t->n_leaves;
+    const size_t n3 = (size_t)(3 * nl);
+    int nt = 1;
+#ifdef _OPENMP
+    nt = omp_get_max_threads();
+    if ((int64_t)nt > n / 256 + 1) nt = (int)(n / 256 + 1);   /* small inputs: fewer copies */
+#endif
+    /* per thread: sum, compensation, and the diagnostics when asked */
+    double *ps = (double *)calloc((size_t)nt * n3, sizeof(double));
+    double *pc = (double *)calloc((size_t)nt * n3, sizeof(double));
+    double *pm = scale ? (double *)calloc((size_t)nt * n3, sizeof(double)) : NULL;
+    double *pa = fabs_sum ? (double *)calloc((size_t)nt * n3, sizeof(double)) : NULL;
+    int64_t *pn = count ? (int64_t *)calloc((size_t)nt * (size_t)nl, sizeof(int64_t)) : NULL;
+#pragma omp parallel num_threads(nt)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        const int64_t k0 = n * tid / nt, k1 = n * (tid + 1) / nt;
+        double *fs = ps + (size_t)tid * n3, *fc = pc + (size_t)tid * n3;
+        for (int64_t k = k0; k < k1; ++k) {
+            stencil st;
+            if (!build_stencil(t, pos + 3 * k, &st, 0)) continue;
+            for (int oz = 0; oz < 3; ++oz)
+                for (int oy = 0; oy < 3; ++oy)
+                    for (int ox = 0; ox < 3; ++ox) {
+                        int q = oz * 9 + oy * 3 + ox;
+                        int64_t j = st.leaf[q];
+                        if (j < 0) continue;
+                        double w = st.ph[0][ox] * st.ph[1][oy] * st.ph[2][oz];
+                        for (int e = 0; e < 3; ++e) {
+                            nsum(&fs[3 * j + e], &fc[3 * j + e], w * F[3 * k + e]);
+                            if (pm) pm[(size_t)tid * n3 + 3 * j + e] += fabs(w * F[3 * k + e]);
+                            if (pa) pa[(size_t)tid * n3 + 3 * j + e] += fabs(F[3 * k + e]);
+                        }
+                        if (pn) pn[(size_t)tid * (size_t)nl + j] += 1;
                     }
-                    if (count) count[j] += 1;
-                }
+        }
     }
-    for (int64_t i = 0; i < 3 * nl; ++i) f[i] += comp[i];
-    free(comp);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < (int64_t)n3; ++i) {
+        double s = 0.0, c = 0.0, m = 0.0, a = 0.0;
+        for (int th = 0; th < nt; ++th) {
+            nsum(&s, &c, ps[(size_t)th * n3 + i]);
+            nsum(&s, &c, pc[(size_t)th * n3 + i]);
+            if (pm) m += pm[(size_t)th * n3 + i];
+            if (pa) a += pa[(size_t)th * n3 + i];
+        }
+        f[i] = s + c;
+        if (scale) scale[i] = m;
+        if (fabs_sum) fabs_sum[i] = a;
+    }
+    if (count) {
+        for (int64_t j = 0; j < nl; ++j) {
+            int64_t c = 0;
+            for (int th = 0; th < nt; ++th) c += pn[(size_t)th * (size_t)nl + j];
+            count[j] = c;
+        }
+    }
+    free(ps);
+    free(pc);
+    free(pm);
+    free(pa);
+    free(pn);
 }
 
 /* ---------------------------------------------------------------------------
@@ -411,7 +472,7 @@ void orc_grad_pos(const orc_tree *t, const double *field, const double *vec, con
     for (int64_t k = 0; k < n; ++k) {
         stencil st;
         double s[3] = {0, 0, 0}, c[3] = {0, 0, 0}, m[3] = {0, 0, 0};
-        if (build_stencil(t, pos + 3 * k, &st)) {
+        if (build_stencil(t, pos + 3 * k, &st, 1)) {
             double h = ldexp(1.0, st.level);
             for (int oz = 0; oz < 3; ++oz)
                 for (int oy = 0; oy < 3; ++oy)
@@ -422,10 +483,10 @@ void orc_grad_pos(const orc_tree *t, const double *field, const double *vec, con
                         const double *v = vec + 3 * k;
                         double dot = v[0] * u[0] + v[1] * u[1] + v[2] * u[2];
                         double adot = fabs(v[0] * u[0]) + fabs(v[1] * u[1]) + fabs(v[2] * u[2]);
-                        double px = orc_phi(st.r[0][ox]), py = orc_phi(st.r[1][oy]), pz = orc_phi(st.r[2][oz]);
-                        double dw[3] = {h * orc_dphi(st.r[0][ox]) * py * pz,
-                                        h * px * orc_dphi(st.r[1][oy]) * pz,
-                                        h * px * py * orc_dphi(st.r[2][oz])};
+                        double px = st.ph[0][ox], py = st.ph[1][oy], pz = st.ph[2][oz];
+                        double dw[3] = {h * st.dph[0][ox] * py * pz,
+                                        h * px * st.dph[1][oy] * pz,
+                                        h * px * py * st.dph[2][oz]};
                         for (int d = 0; d < 3; ++d) {
                             nsum(&s[d], &c[d], dot * dw[d]);
                             m[d] += adot * fabs(dw[d]);
@@ -447,7 +508,7 @@ void orc_stencil_leaves(const orc_tree *t, const double *pos, int64_t n, int64_t
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < n; ++k) {
         stencil st;
-        int ok = build_stencil(t, pos + 3 * k, &st);
+        int ok = build_stencil(t, pos + 3 * k, &st, 0);
         host[k] = ok ? st.host : -1;
         level[k] = ok ? st.level : -1;
         for (int q = 0; q < 27; ++q) nodes[27 * k + q] = ok ? st.leaf[q] : -1;

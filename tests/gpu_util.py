@@ -56,12 +56,11 @@ def fixed_point_quantum(forces: np.ndarray) -> float:
 
 TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
 
-# Absolute precision of a delta weight computed in FP64 from the phi formula:
-# its outer branch cancels to zero at |r| = 3/2, so a computed weight is only
-# good to ~eps absolute (not relative).  A leaf that receives nothing but
-# edge-of-support weights therefore carries an absolute error ~eps * sum |F|
-# in any FP64 evaluation, the oracle's included.
-ETA = 2.0 ** -46
+# Absolute precision of the oracle's delta weights: the printed phi formula is
+# evaluated in binary128, whose outer branch (cancelling towards |r| = 3/2)
+# is good to about 2^-113 absolute.  A leaf fed only by edge-of-support
+# weights can hold a value of that order, so the bound keeps this term.
+ETA = 2.0 ** -110
 
 
 def spread_bound(S, A, cnt, dtype, quantum=None):

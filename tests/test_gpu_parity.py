@@ -200,7 +200,7 @@ def test_spread_fixed_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
     f, S, cnt, A = o.spread(frc, pts, with_scale=True)
     got = cfg1_gpu.spread(to_dev(frc, dtype), to_dev(pts, dtype), mode="fixed").cpu().numpy()
     # the quantisation term dominates in FP64; FP32 adds its own rounding
-    assert spread_excess(got, f, S, A, cnt, torch.float32, fixed_point_quantum(frc)) <= 1.0
+    assert spread_excess(got, f, S, A, cnt, dtype, fixed_point_quantum(frc)) <= 1.0
 
 
 def test_fixed_point_is_bitwise_reproducible(ot, cfg1, cfg1_gpu):
@@ -293,7 +293,7 @@ def test_grad_pos_parity_cfg1(ot, cfg1, cfg1_gpu, dtype):
     pts, frc, fld = _inputs(w, o, dtype)
     g, S = o.grad_pos(fld, frc, pts, with_scale=True)
     got = cfg1_gpu.grad_pos(to_dev(fld, dtype), to_dev(frc, dtype), to_dev(pts, dtype)).cpu().numpy()
-    assert scaled_err(got, g, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
+    assert scaled_err(got, g, S) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -309,7 +309,7 @@ def test_interp_backward_one_pass_cfg1(ot, cfg1, cfg1_gpu, dtype):
     assert torch.equal(gf, cfg1_gpu.spread(G, P, mode="fixed"))
     assert torch.equal(gx, cfg1_gpu.grad_pos(Fd, G, P))
     want, S = o.grad_pos(fld, g, pts, with_scale=True)
-    assert scaled_err(gx.cpu().numpy(), want, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
+    assert scaled_err(gx.cpu().numpy(), want, S) <= TOL[dtype]
     f, Sf, cnt, A = o.spread(g, pts, with_scale=True)
     assert spread_excess(gf.cpu().numpy(), f, Sf, A, cnt, dtype, fixed_point_quantum(g)) <= 1.0
     # one output at a time, and accumulation into the field's gradient
@@ -337,7 +337,7 @@ def test_spread_backward_one_pass_cfg1(ot, cfg1, cfg1_gpu, dtype):
     U, S = o.interpolate(gfield, pts, with_scale=True)
     assert scaled_err(gF.cpu().numpy(), U, S) <= TOL[dtype]
     want, S = o.grad_pos(gfield, frc, pts, with_scale=True)
-    assert scaled_err(gx.cpu().numpy(), want, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
+    assert scaled_err(gx.cpu().numpy(), want, S) <= TOL[dtype]
     gF1, none = cfg1_gpu.spread_backward(Gf, F, P, need_pos=False)
     assert none is None and torch.equal(gF1, gF)
 
@@ -358,7 +358,7 @@ def test_backward_one_pass_nonperiodic(ot, dtype):
     f, Sf, cnt, A = o.spread(g, pts, with_scale=True)
     assert spread_excess(gf.cpu().numpy(), f, Sf, A, cnt, dtype) <= 1.0
     want, S = o.grad_pos(fld, g, pts, with_scale=True)
-    assert scaled_err(gx.cpu().numpy(), want, S) <= (1e-11 if dtype == torch.float64 else 2e-5)
+    assert scaled_err(gx.cpu().numpy(), want, S) <= TOL[dtype]
     gF, gx2 = t.spread_backward(Fd, G, P)     # the same contraction: field with the vectors G
     assert torch.equal(gx2, gx)
     U, S = o.interpolate(fld, pts, with_scale=True)

@@ -263,7 +263,7 @@ def test_cfg5_autograd_against_oracle(ot, cfg2):
     gu = u.grad.cpu().numpy()
     k = np.sort(rng.choice(pts.shape[0], size=20000, replace=False))
     want, S = o.grad_pos(fld, g[k], pts[k], with_scale=True)
-    assert scaled_err(gx[k], want, S) <= 2e-5
+    assert scaled_err(gx[k], want, S) <= TOL[dt]
     # grad of the field = spread of the upstream gradient (sampled leaves)
     leaves = _sample_leaves(o, rng, 100)
     near = _near_points(pts, _leaf_centres(o, leaves), max(0, o.l_min - 2))

@@ -93,6 +93,41 @@ def test_dphi_continuous_and_moments(orc):
         assert sum(orc.phi(d) * p for d, p in zip(ds, dp)) == pytest.approx(0.0, abs=1e-13)
 
 
+def _edge_phi_conjugate(eps):
+    """phi(3/2 - eps) from the outer branch multiplied by its conjugate:
+    (1/2 + 3 eps)^2 - (1/4 + 3 eps - 3 eps^2) = 12 eps^2, so
+    phi = 2 eps^2 / (1/2 + 3 eps + sqrt(1/4 + 3 eps - 3 eps^2)), a form with no
+    cancellation, evaluated here in 60-digit decimal arithmetic."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    e = Decimal(eps)
+    return float(2 * e * e / (Decimal("0.5") + 3 * e + (Decimal("0.25") + 3 * e - 3 * e * e).sqrt()))
+
+
+def _edge_dphi_conjugate(eps):
+    """phi'(3/2 - eps) = -eps (7 - 6 eps + q) / (q (1 + q)), q = sqrt(1 + 12 eps - 12 eps^2),
+    the derivative branch rewritten the same way (60-digit decimal)."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    e = Decimal(eps)
+    q = (1 + 12 * e - 12 * e * e).sqrt()
+    return float(-e * (7 - 6 * e + q) / (q * (1 + q)))
+
+
+@pytest.mark.parametrize("k", [4, 10, 20, 30, 40, 50])
+def test_phi_edge_of_support_relative_accuracy(orc, k):
+    """Near |r| = 3/2 the printed outer branch cancels; evaluated in FP64 it is
+    only ~2^-53 absolute (wrong in every digit for eps below ~2^-27).  The
+    oracle evaluates it in binary128: FP64-relative precision plus about
+    2^-113 absolute."""
+    eps = 2.0 ** -k
+    for r, sgn in ((1.5 - eps, 1.0), (-(1.5 - eps), -1.0)):
+        want = _edge_phi_conjugate(eps)
+        assert orc.phi(r) == pytest.approx(want, rel=4e-16, abs=2.0 ** -110), (k, r)
+        dwant = sgn * _edge_dphi_conjugate(eps)
+        assert orc.dphi(r) == pytest.approx(dwant, rel=4e-16, abs=2.0 ** -108), (k, r)
+
+
 # ---------------------------------------------------------------------------
 # Morton order
 # ---------------------------------------------------------------------------
