@@ -40,6 +40,17 @@
  *   - `stream` is a hipStream_t (NULL = default stream).  Calls enqueue work
  *     and return; results are ready when the stream reaches them.  Only
  *     ot_build_tree synchronises (once, to report validation errors).
+ *   - A tree handle is read-only after ot_build_tree: every call that needs
+ *     working memory takes it from the caller (a `work` argument), from its
+ *     batch plan, or allocates it on the call's stream, so calls on one tree
+ *     may run on several streams at once.
+ *   - Host ids (`ids` arguments marked "input"): the host leaf of every point
+ *     as ot_locate returns it (Algorithm 1's host_cell_id, which Sec. 3.2
+ *     makes the prerequisite of interpolation and spreading).  When given,
+ *     the call takes each point's host from it instead of searching the
+ *     tree; -1 or an id outside [0, n_leaves) means "no host".  NULL: the
+ *     call searches.  Ids that are not the points' hosts give meaningless
+ *     (but in-bounds) results.
  *   - Return value: OT_OK (0) or a negative OT_ERR_* code; ot_last_error()
  *     returns a message for the calling thread's last failure.
  */
@@ -106,7 +117,8 @@ typedef struct {
     int32_t l_min, l_max, periodic;
     int32_t table_levels;    /* levels of the descent table (root + sub-tables)      */
     int64_t table_bytes;     /* device bytes of the descent table                    */
-    int64_t workspace_bytes; /* device bytes of the fixed-point spreading workspace   */
+    int64_t workspace_bytes; /* bytes of a fixed-point spreading workspace (the       */
+                             /* caller's `work`), = ot_spread_workspace_bytes        */
 } ot_tree_info;
 
 /* Tuning of the batched persistent pass.  Zero fields take defaults: 256
@@ -127,6 +139,16 @@ typedef struct {
  * Neighbouring threads then share stencil nodes in cache and in the
  * workgroup's spreading table.  Needs the same ops for every instance. */
 #define OT_TUNE_SORT_POINTS 1
+
+/* Sorted plans whose instances interpolate or spread (without gradient ops)
+ * run a host-major pass: each window of 256 sorted points is ranked by host
+ * in LDS, every distinct host's 27 node leaves and field values are taken
+ * once and shared by its points, and the points' spreading sums for one
+ * host are added up in registers before one LDS add per node and component
+ * (the same rounded fixed-point contributions, so FIXED results are equal
+ * bit for bit).  Windows whose hosts are too spread out go to the per-point
+ * pass.  OT_TUNE_PER_POINT keeps such plans on the per-point pass. */
+#define OT_TUNE_PER_POINT 2
 
 /* Morton keys of leaf anchors (Sec. 3.1: leaves are ordered along the
  * Z-curve).  anchors: (n, 3) uint32, each < 2^l_max.  keys: (n,) uint64.
@@ -165,34 +187,52 @@ int ot_locate(const ot_tree *tree, const void *pos, int32_t dtype, int64_t n, in
               void *stream);
 
 /* Interpolation (Sec. 2.2): vel[k] = sum over the 27 stencil nodes of
- * w_kn field[leaf(n)].  field: (n_leaves, 3) in leaf-id order. */
-int ot_interpolate(const ot_tree *tree, const void *field, const void *pos, int32_t dtype,
-                   int64_t n, void *vel, void *stream);
+ * w_kn field[leaf(n)].  field: (n_leaves, 3) in leaf-id order.  ids: input
+ * host ids (nullable, see the conventions). */
+int ot_interpolate(const ot_tree *tree, const void *field, const void *pos, const int32_t *ids,
+                   int32_t dtype, int64_t n, void *vel, void *stream);
+
+/* Bytes of the workspace of fixed-point spreading on `tree`: a 256-byte
+ * header and n_leaves x 3 int64 accumulators (0 for a NULL tree). */
+int64_t ot_spread_workspace_bytes(const ot_tree *tree);
 
 /* Spreading (Sec. 2.2): field_out[j] (+)= sum_k sum_{n: leaf(n) = j} w_kn
  * force[k], the exact transpose of ot_interpolate.  accumulate = 0 overwrites
- * field_out, 1 adds to it.  mode: OT_SPREAD_ATOMIC or OT_SPREAD_FIXED.  Uses
- * the tree's workspace in FIXED mode: FIXED calls on one tree must not run
- * concurrently on different streams. */
-int ot_spread(const ot_tree *tree, const void *force, const void *pos, int32_t dtype, int64_t n,
-              int32_t mode, int32_t accumulate, void *field_out, void *stream);
+ * field_out, 1 adds to it.  mode: OT_SPREAD_ATOMIC or OT_SPREAD_FIXED.  ids:
+ * input host ids (nullable).  work: FIXED mode's workspace, a 256-byte
+ * aligned device buffer of ot_spread_workspace_bytes(tree) bytes owned by
+ * the caller (calls sharing one must not overlap); NULL: the call allocates
+ * it on `stream` (hipMallocAsync) and frees it there.  ATOMIC mode ignores
+ * it.  Errors: OT_ERR_INVALID (NULL arrays, bad mode/dtype, n < 0, misaligned
+ * work), OT_ERR_OOM, OT_ERR_HIP. */
+int ot_spread(const ot_tree *tree, const void *force, const void *pos, const int32_t *ids, int32_t dtype,
+              int64_t n, int32_t mode, int32_t accumulate, void *field_out, void *work, void *stream);
 
 /* One fused pass over the points: host search, interpolation of `field`
- * and spreading of `force` share the stencil.  ops: OT_OP_* bits; ids,
- * vel, force/field_out may be NULL when their op is off.  field_out is
- * overwritten (accumulate = 0) or added to (1). */
+ * and spreading of `force` share the stencil.  ops: OT_OP_* bits; ids
+ * (output of the search), vel, force/field_out may be NULL when their op is
+ * off.  field_out is overwritten (accumulate = 0) or added to (1).  work: as
+ * ot_spread. */
 int ot_track(const ot_tree *tree, int32_t ops, const void *field, const void *force,
              const void *pos, int32_t dtype, int64_t n, int32_t mode, int32_t accumulate,
-             int32_t *ids, void *vel, void *field_out, void *stream);
+             int32_t *ids, void *vel, void *field_out, void *work, void *stream);
 
-/* Position gradient through the delta-function derivative:
+/* Position gradient through the delta-function derivative (the phi
+ * equation of Sec. 2.2, differentiated branch by branch):
  * grad[k, d] = sum_n (vec[k] . field[leaf(n)]) dw_kn/dX_d with
  * dw/dX_d = 2^l phi'(r_d) prod_{e != d} phi(r_e), the host leaf held fixed.
- * With field = interpolated field and vec = dLoss/dvel this is the gradient
- * of interpolate; with field = dLoss/dfield_out and vec = force it is the
- * gradient of spread.  grad: (n, 3). */
+ * ids: input host ids (nullable).  grad: (n, 3).
+ *
+ * ot_interp_grad_pos: gradient of sum_k grad_vel[k] . vel[k] for
+ * vel = ot_interpolate(field) at pos, i.e. ot_grad_pos(field, vec = grad_vel).
+ * ot_spread_grad_pos: gradient of sum_j grad_field[j] . field_out[j] for
+ * field_out = ot_spread(force) at pos, i.e. ot_grad_pos(grad_field, vec = force). */
 int ot_grad_pos(const ot_tree *tree, const void *field, const void *vec, const void *pos,
-                int32_t dtype, int64_t n, void *grad, void *stream);
+                const int32_t *ids, int32_t dtype, int64_t n, void *grad, void *stream);
+int ot_interp_grad_pos(const ot_tree *tree, const void *field, const void *grad_vel, const void *pos,
+                       const int32_t *ids, int32_t dtype, int64_t n, void *grad_pos, void *stream);
+int ot_spread_grad_pos(const ot_tree *tree, const void *grad_field, const void *force, const void *pos,
+                       const int32_t *ids, int32_t dtype, int64_t n, void *grad_pos, void *stream);
 
 /* Backward of ot_interpolate in one pass over the points (the adjoint pair
  * of Sec. 2.2: spreading is the transpose of interpolation), sharing the
@@ -202,21 +242,23 @@ int ot_grad_pos(const ot_tree *tree, const void *field, const void *vec, const v
  * field: (n_leaves, 3) forward field; grad_vel: (n, 3) dLoss/dvel.  Either
  * output may be NULL (not computed), not both unless n = 0 (then the call
  * only clears grad_field when given and accumulate = 0).  grad_field: (n_leaves, 3);
- * grad_pos: (n, 3).  Uses the tree's workspace in FIXED mode, like
- * ot_spread.  Errors: OT_ERR_INVALID for NULL inputs that an output needs,
- * a bad mode or dtype, n < 0. */
+ * grad_pos: (n, 3).  ids: input host ids (nullable); work: FIXED mode's
+ * workspace, as ot_spread.  Errors: OT_ERR_INVALID for NULL inputs that an
+ * output needs, a bad mode or dtype, n < 0. */
 int ot_interp_backward(const ot_tree *tree, const void *field, const void *grad_vel, const void *pos,
-                       int32_t dtype, int64_t n, int32_t mode, int32_t accumulate, void *grad_field,
-                       void *grad_pos, void *stream);
+                       const int32_t *ids, int32_t dtype, int64_t n, int32_t mode, int32_t accumulate,
+                       void *grad_field, void *grad_pos, void *work, void *stream);
 
 /* Backward of ot_spread in one pass over the points:
  *   grad_force = interpolate(grad_field)          (as ot_interpolate)
  *   grad_pos   = ot_grad_pos(grad_field, force)   (host leaf held fixed).
  * grad_field: (n_leaves, 3) dLoss/dfield_out; force: (n, 3) forward forces.
  * Either output may be NULL, not both unless n = 0 (then nothing is done);
- * both are (n, 3) and overwritten.  Errors as ot_interp_backward. */
+ * both are (n, 3) and overwritten.  ids: input host ids (nullable).  Errors
+ * as ot_interp_backward. */
 int ot_spread_backward(const ot_tree *tree, const void *grad_field, const void *force, const void *pos,
-                       int32_t dtype, int64_t n, void *grad_force, void *grad_pos, void *stream);
+                       const int32_t *ids, int32_t dtype, int64_t n, void *grad_force, void *grad_pos,
+                       void *stream);
 
 /* Multi-direct forcing of the immersed-boundary method (IBM subsection of
  * Sec. 2.2), n_iter iterations of:
@@ -325,7 +367,10 @@ int ot_mdf(const ot_tree *tree, void *field, const void *pos, const void *target
  * owns points [offsets[i], offsets[i+1]).  ops: host (n_inst,) OT_OP_* bits
  * per instance.  Tiles of <= tuning.tile points never straddle instances.
  * The plan copies offsets/ops; it keeps the tree pointer (destroy the plan
- * before the tree). */
+ * before the tree).  A FIXED plan that spreads owns its spreading workspace,
+ * so plans on one tree may run on different streams at once.  With
+ * OT_TUNE_SORT_POINTS an instance with ops = 0 must be empty
+ * (OT_ERR_INVALID otherwise). */
 int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets, const int32_t *ops,
                          int32_t n_inst, int32_t dtype, int32_t mode, const ot_tuning *tuning,
                          ot_batch_plan **out);
@@ -357,6 +402,12 @@ int ot_batch_last_kernel_ms(const ot_batch_plan *plan, float *ms);
 
 /* Tiles and workgroups a plan uses (host ints, either may be NULL). */
 int ot_batch_plan_shape(const ot_batch_plan *plan, int64_t *n_tiles, int32_t *grid);
+
+/* Host-major plans (see OT_TUNE_PER_POINT): the number of 256-point windows
+ * (0 for other plans) and how many of them the last completed run handed to
+ * the per-point pass (host ints, either may be NULL).  Synchronises with the
+ * device to read the count. */
+int ot_batch_plan_windows(const ot_batch_plan *plan, int64_t *n_windows, int64_t *handed_over);
 
 int ot_batch_plan_destroy(ot_batch_plan *plan);
 

@@ -57,6 +57,7 @@ class Tuning(ctypes.Structure):
 
 
 OT_TUNE_SORT_POINTS = 1
+OT_TUNE_PER_POINT = 2
 
 
 EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_get", "ot_tree_leaves",
@@ -64,7 +65,8 @@ EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_g
            "ot_batch_run", "ot_batch_plan_shape", "ot_batch_plan_timing", "ot_batch_last_kernel_ms",
            "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums",
            "ot_relocate", "ot_leaf_splitters", "ot_find_owner", "ot_particle_step", "ot_interp_backward",
-           "ot_spread_backward", "ot_batch_run_grad")
+           "ot_spread_backward", "ot_batch_run_grad", "ot_interp_grad_pos", "ot_spread_grad_pos",
+           "ot_spread_workspace_bytes", "ot_batch_plan_windows")
 
 
 def _load():
@@ -80,16 +82,19 @@ def _load():
         "ot_tree_info_get": [P, ctypes.POINTER(TreeInfo)],
         "ot_tree_leaves": [P, P, P, P],
         "ot_locate": [P, P, i32, i64, P, P],
-        "ot_interpolate": [P, P, P, i32, i64, P, P],
-        "ot_spread": [P, P, P, i32, i64, i32, i32, P, P],
-        "ot_track": [P, i32, P, P, P, i32, i64, i32, i32, P, P, P, P],
-        "ot_grad_pos": [P, P, P, P, i32, i64, P, P],
-        "ot_interp_backward": [P, P, P, P, i32, i64, i32, i32, P, P, P],
-        "ot_spread_backward": [P, P, P, P, i32, i64, P, P, P],
+        "ot_interpolate": [P, P, P, P, i32, i64, P, P],
+        "ot_spread": [P, P, P, P, i32, i64, i32, i32, P, P, P],
+        "ot_track": [P, i32, P, P, P, i32, i64, i32, i32, P, P, P, P, P],
+        "ot_grad_pos": [P, P, P, P, P, i32, i64, P, P],
+        "ot_interp_grad_pos": [P, P, P, P, P, i32, i64, P, P],
+        "ot_spread_grad_pos": [P, P, P, P, P, i32, i64, P, P],
+        "ot_interp_backward": [P, P, P, P, P, i32, i64, i32, i32, P, P, P, P],
+        "ot_spread_backward": [P, P, P, P, P, i32, i64, P, P, P],
         "ot_batch_plan_create": [P, P, P, i32, i32, i32, ctypes.POINTER(Tuning), ctypes.POINTER(P)],
         "ot_batch_run": [P, P, P, P, P, P, P, P],
         "ot_batch_run_grad": [P, P, P, P, P, P, P, P, P],
         "ot_batch_plan_shape": [P, ctypes.POINTER(i64), ctypes.POINTER(i32)],
+        "ot_batch_plan_windows": [P, ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "ot_batch_plan_timing": [P, i32],
         "ot_batch_last_kernel_ms": [P, ctypes.POINTER(ctypes.c_float)],
         "ot_batch_plan_destroy": [P],
@@ -106,6 +111,8 @@ def _load():
         fn.restype = ctypes.c_int
     L.ot_mdf_workspace_bytes.argtypes = [P, i64, i32]
     L.ot_mdf_workspace_bytes.restype = i64
+    L.ot_spread_workspace_bytes.argtypes = [P]
+    L.ot_spread_workspace_bytes.restype = i64
     L.ot_strerror.argtypes = [i32]
     L.ot_strerror.restype = ctypes.c_char_p
     L.ot_last_error.argtypes = []
@@ -152,6 +159,15 @@ def _check_out(t: Optional[torch.Tensor], rows: int, dtype, device, name: str) -
         raise ValueError(f"{name}: needs a contiguous {dtype} device tensor with {rows} rows")
 
 
+def _host_ids(ids: Optional[torch.Tensor], n: int, device) -> Optional[torch.Tensor]:
+    """Validate caller-given host ids (int32, one per point) or pass None."""
+    if ids is None:
+        return None
+    if ids.dtype != torch.int32 or ids.numel() != n or not ids.is_contiguous() or ids.device != device:
+        raise ValueError("ids must be a contiguous int32 tensor with one host id per point, on the points' device")
+    return ids
+
+
 def _mode_code(mode) -> int:
     if mode in ("atomic", OT_SPREAD_ATOMIC):
         return OT_SPREAD_ATOMIC
@@ -191,6 +207,22 @@ class Tree:
         self.l_min, self.l_max, self.periodic = int(l_min), int(l_max), bool(periodic)
         self.n_leaves = int(n)
         self.device = keys.device
+        self.ws_bytes = int(lib.ot_spread_workspace_bytes(h))
+
+    def workspace(self) -> torch.Tensor:
+        """A fixed-point spreading workspace for this tree (``ot_spread``'s
+        ``work``); the caching allocator hands out 512-byte aligned blocks."""
+        return torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+
+    def _work(self, mode, work: Optional[torch.Tensor]):
+        if _mode_code(mode) != OT_SPREAD_FIXED:
+            return None
+        if work is None:
+            return self.workspace()
+        if work.device != self.device or work.numel() * work.element_size() < self.ws_bytes or \
+                work.data_ptr() % 256:
+            raise ValueError(f"work must be a 256-byte aligned device buffer of {self.ws_bytes} bytes")
+        return work
 
     @classmethod
     def from_anchors(cls, anchors: torch.Tensor, levels: torch.Tensor, l_min: int, l_max: int,
@@ -235,19 +267,25 @@ class Tree:
         _check(lib.ot_locate(self._h, _ptr(pos), _dtype_code(pos), pos.shape[0], _ptr(ids), _stream()))
         return ids
 
-    def interpolate(self, field: torch.Tensor, pos: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def interpolate(self, field: torch.Tensor, pos: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    ids: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Velocities at pos; ids: the points' host ids when already known (skips the search)."""
         pos = _rows3(pos, "pos")
         field = _rows3(field, "field")
         if field.dtype != pos.dtype or field.shape[0] != self.n_leaves:
             raise ValueError("field must be (n_leaves, 3) with the dtype of pos")
         _check_out(out, pos.shape[0], pos.dtype, pos.device, "out")
+        ids = _host_ids(ids, pos.shape[0], pos.device)
         vel = out if out is not None else torch.empty_like(pos)
-        _check(lib.ot_interpolate(self._h, _ptr(field), _ptr(pos), _dtype_code(pos), pos.shape[0], _ptr(vel),
-                                  _stream()))
+        _check(lib.ot_interpolate(self._h, _ptr(field), _ptr(pos), _ptr(ids), _dtype_code(pos), pos.shape[0],
+                                  _ptr(vel), _stream()))
         return vel
 
     def spread(self, force: torch.Tensor, pos: torch.Tensor, mode="atomic", out: Optional[torch.Tensor] = None,
-               accumulate: bool = False) -> torch.Tensor:
+               accumulate: bool = False, ids: Optional[torch.Tensor] = None,
+               work: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Leaf field of the spread forces; ids: known host ids; work: FIXED mode's workspace
+        (``workspace()``; a fresh one per call when None)."""
         pos = _rows3(pos, "pos")
         force = _rows3(force, "force")
         if force.dtype != pos.dtype or force.shape[0] != pos.shape[0]:
@@ -256,14 +294,17 @@ class Tree:
             out = torch.empty((self.n_leaves, 3), dtype=pos.dtype, device=pos.device)
             accumulate = False
         _check_out(out, self.n_leaves, pos.dtype, pos.device, "out")
-        _check(lib.ot_spread(self._h, _ptr(force), _ptr(pos), _dtype_code(pos), pos.shape[0], _mode_code(mode),
-                             1 if accumulate else 0, _ptr(out), _stream()))
+        ids = _host_ids(ids, pos.shape[0], pos.device)
+        work = self._work(mode, work)
+        _check(lib.ot_spread(self._h, _ptr(force), _ptr(pos), _ptr(ids), _dtype_code(pos), pos.shape[0],
+                             _mode_code(mode), 1 if accumulate else 0, _ptr(out), _ptr(work), _stream()))
         return out
 
     def track(self, pos: torch.Tensor, field: Optional[torch.Tensor] = None, force: Optional[torch.Tensor] = None,
               ops: int = OT_OP_LOCATE | OT_OP_INTERPOLATE | OT_OP_SPREAD, mode="atomic",
               ids: Optional[torch.Tensor] = None, vel: Optional[torch.Tensor] = None,
-              field_out: Optional[torch.Tensor] = None, accumulate: bool = False):
+              field_out: Optional[torch.Tensor] = None, accumulate: bool = False,
+              work: Optional[torch.Tensor] = None):
         """Fused pass: returns (ids, vel, field_out) (None where the op is off)."""
         pos = _rows3(pos, "pos")
         n = pos.shape[0]
@@ -285,13 +326,18 @@ class Tree:
         _check_out(ids, n, torch.int32, pos.device, "ids")
         _check_out(vel, n, pos.dtype, pos.device, "vel")
         _check_out(field_out, self.n_leaves, pos.dtype, pos.device, "field_out")
+        work = self._work(mode, work) if ops & OT_OP_SPREAD else None
         _check(lib.ot_track(self._h, ops, _ptr(field), _ptr(force), _ptr(pos), _dtype_code(pos), n,
                             _mode_code(mode), 1 if accumulate else 0, _ptr(ids), _ptr(vel), _ptr(field_out),
-                            _stream()))
+                            _ptr(work), _stream()))
         return ids, vel, field_out
 
     def grad_pos(self, field: torch.Tensor, vec: torch.Tensor, pos: torch.Tensor,
-                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                 out: Optional[torch.Tensor] = None, ids: Optional[torch.Tensor] = None,
+                 entry: str = "ot_grad_pos") -> torch.Tensor:
+        """Position gradient sum_n (vec . field[leaf(n)]) grad w (``entry`` picks the C entry point:
+        ot_grad_pos, ot_interp_grad_pos (field, vec = grad_vel) or ot_spread_grad_pos (field = grad_field,
+        vec = force); all three compute the same sum)."""
         pos = _rows3(pos, "pos")
         field = _rows3(field, "field")
         vec = _rows3(vec, "vec")
@@ -300,14 +346,18 @@ class Tree:
         if field.dtype != pos.dtype or vec.dtype != pos.dtype:
             raise ValueError("field, vec and pos must share a dtype")
         _check_out(out, pos.shape[0], pos.dtype, pos.device, "out")
+        ids = _host_ids(ids, pos.shape[0], pos.device)
+        if entry not in ("ot_grad_pos", "ot_interp_grad_pos", "ot_spread_grad_pos"):
+            raise ValueError(f"unknown gradient entry point {entry!r}")
         g = out if out is not None else torch.empty_like(pos)
-        _check(lib.ot_grad_pos(self._h, _ptr(field), _ptr(vec), _ptr(pos), _dtype_code(pos), pos.shape[0],
-                               _ptr(g), _stream()))
+        _check(getattr(lib, entry)(self._h, _ptr(field), _ptr(vec), _ptr(pos), _ptr(ids), _dtype_code(pos),
+                                   pos.shape[0], _ptr(g), _stream()))
         return g
 
     def interp_backward(self, field: torch.Tensor, grad_vel: torch.Tensor, pos: torch.Tensor, mode="atomic",
                         need_field: bool = True, need_pos: bool = True, accumulate: bool = False,
-                        grad_field: Optional[torch.Tensor] = None, grad_pos: Optional[torch.Tensor] = None):
+                        grad_field: Optional[torch.Tensor] = None, grad_pos: Optional[torch.Tensor] = None,
+                        ids: Optional[torch.Tensor] = None, work: Optional[torch.Tensor] = None):
         """Backward of `interpolate` in one pass: (spread(grad_vel), grad_pos(field, grad_vel)); an output
         not asked for is None."""
         pos = _rows3(pos, "pos")
@@ -327,13 +377,15 @@ class Tree:
         if need_pos:
             _check_out(grad_pos, pos.shape[0], pos.dtype, pos.device, "grad_pos")
             gx = grad_pos if grad_pos is not None else torch.empty_like(pos)
-        _check(lib.ot_interp_backward(self._h, _ptr(field), _ptr(grad_vel), _ptr(pos), _dtype_code(pos),
+        ids = _host_ids(ids, pos.shape[0], pos.device)
+        work = self._work(mode, work) if need_field else None
+        _check(lib.ot_interp_backward(self._h, _ptr(field), _ptr(grad_vel), _ptr(pos), _ptr(ids), _dtype_code(pos),
                                       pos.shape[0], _mode_code(mode), 1 if accumulate else 0, _ptr(gf), _ptr(gx),
-                                      _stream()))
+                                      _ptr(work), _stream()))
         return gf, gx
 
     def spread_backward(self, grad_field: torch.Tensor, force: torch.Tensor, pos: torch.Tensor,
-                        need_force: bool = True, need_pos: bool = True):
+                        need_force: bool = True, need_pos: bool = True, ids: Optional[torch.Tensor] = None):
         """Backward of `spread` in one pass: (interpolate(grad_field), grad_pos(grad_field, force)); an output
         not asked for is None."""
         pos = _rows3(pos, "pos")
@@ -347,7 +399,8 @@ class Tree:
             raise ValueError("nothing to compute")
         gF = torch.empty_like(pos) if need_force else None
         gx = torch.empty_like(pos) if need_pos else None
-        _check(lib.ot_spread_backward(self._h, _ptr(grad_field), _ptr(force), _ptr(pos), _dtype_code(pos),
+        ids = _host_ids(ids, pos.shape[0], pos.device)
+        _check(lib.ot_spread_backward(self._h, _ptr(grad_field), _ptr(force), _ptr(pos), _ptr(ids), _dtype_code(pos),
                                       pos.shape[0], _ptr(gF), _ptr(gx), _stream()))
         return gF, gx
 
@@ -454,10 +507,12 @@ class BatchPlan:
     """Many point sets in one persistent, graph-replayed pass (``ot_batch_*``)."""
 
     def __init__(self, tree: Tree, offsets: Sequence[int], ops: Sequence[int], dtype=torch.float32,
-                 mode="atomic", block: int = 0, tile: int = 0, grid: int = 0, sort_points: bool = False):
+                 mode="atomic", block: int = 0, tile: int = 0, grid: int = 0, sort_points: bool = False,
+                 per_point: bool = False):
         off = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
         opa = (ctypes.c_int32 * len(ops))(*[int(v) for v in ops])
-        tun = Tuning(block, tile, grid, OT_TUNE_SORT_POINTS if sort_points else 0)
+        tun = Tuning(block, tile, grid, (OT_TUNE_SORT_POINTS if sort_points else 0) |
+                     (OT_TUNE_PER_POINT if per_point else 0))
         h = ctypes.c_void_p()
         code = OT_F32 if dtype == torch.float32 else OT_F64
         _check(lib.ot_batch_plan_create(tree.handle, off, opa, len(ops), code, _mode_code(mode), ctypes.byref(tun),
@@ -472,6 +527,12 @@ class BatchPlan:
         nt, g = ctypes.c_int64(), ctypes.c_int32()
         _check(lib.ot_batch_plan_shape(self._h, ctypes.byref(nt), ctypes.byref(g)))
         return nt.value, g.value
+
+    def windows(self) -> Tuple[int, int]:
+        """(windows of the host-major pass, windows the last run handed to the per-point pass)."""
+        nw, fb = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.ot_batch_plan_windows(self._h, ctypes.byref(nw), ctypes.byref(fb)))
+        return nw.value, fb.value
 
     def set_timing(self, enable: bool) -> None:
         _check(lib.ot_batch_plan_timing(self._h, 1 if enable else 0))

@@ -1,7 +1,10 @@
 """Compile the HIP sources under csrc/ into libocttrack.so (gfx950).
 
 Objects are compiled in parallel with hipcc and linked into one shared
-library next to this file.  The build always recompiles.
+library next to this file.  The build always recompiles.  Files named
+*_inst.hip hold the instantiations of a kernel template and are compiled
+once per (precision, spreading mode), so that the largest kernels build in
+parallel.
 """
 from __future__ import annotations
 
@@ -28,8 +31,8 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, obj: str) -> None:
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def _compile(src: str, obj: str, extra=()) -> None:
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {os.path.basename(src)}:\n{r.stderr}")
@@ -39,14 +42,36 @@ def _compile(src: str, obj: str) -> None:
         sys.stderr.write("\n".join(errs) + "\n")
 
 
+# (suffix, defines) of the instantiations of every *_inst.hip file
+INST = [("f32_atomic", ["-DOT_INST_T=float", "-DOT_INST_MODE=0"]),
+        ("f32_fixed", ["-DOT_INST_T=float", "-DOT_INST_MODE=1"]),
+        ("f64_atomic", ["-DOT_INST_T=double", "-DOT_INST_MODE=0"]),
+        ("f64_fixed", ["-DOT_INST_T=double", "-DOT_INST_MODE=1"])]
+
+
+def _units(bdir: str):
+    """(source, object, extra flags) of every object of the library."""
+    out = []
+    for src in sorted(glob.glob(os.path.join(CSRC, "*.hip"))):
+        base = os.path.basename(src)[:-4]
+        if base.endswith("_inst"):
+            for suf, defs in INST:
+                out.append((src, os.path.join(bdir, f"{base}_{suf}.o"), defs))
+        else:
+            out.append((src, os.path.join(bdir, base + ".o"), []))
+    return out
+
+
 def build(verbose: bool = False) -> str:
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = [os.path.join(bdir, os.path.basename(s)[:-4] + ".o") for s in srcs]
-    jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
+    units = _units(bdir)
+    objs = [o for _, o, _ in units]
+    jobs = min(len(units), int(os.environ.get("MAX_JOBS", "8")))
+    # the slowest units first, so that they do not start last
+    units.sort(key=lambda u: 0 if u[2] else 1)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        list(ex.map(lambda so: _compile(*so), zip(srcs, objs)))
+        list(ex.map(lambda u: _compile(*u), units))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

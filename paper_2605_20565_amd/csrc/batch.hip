@@ -12,164 +12,25 @@
 #include <cstring>
 #include <vector>
 
+#include "batch_plan.h"
 #include "ot_common.h"
 #include "point_sort.h"
 #include "track_device.h"
 
-namespace ot {
-int spread_begin(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
-int spread_scale(const ot_tree *t, int dtype, int mode, const void *force, int64_t n, hipStream_t s);
-int spread_epilogue(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
-}  // namespace ot
-
-struct ot_batch_plan {
-    const ot_tree *tree;
-    int dtype, mode;
-    int block, tile, grid;
-    int ops_union;
-    int64_t n_points, n_tiles;
-    int64_t *tile_start;      // device
-    uint32_t *tile_info;      // device: count | ops << 24
-    unsigned *counter;        // device
-    hipStream_t capture_stream;
-    bool have_graph;
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-    const void *key[7];
-    bool timing;              // record ev[0]/ev[1] around the persistent kernel
-    hipEvent_t ev[2];
-    // point sorting (OT_TUNE_SORT_POINTS)
-    bool sort_points;
-    int sort_bits, sort_shift;
-    int ops_all;              // the common ops of every instance
-    bool grad_plan;           // instances carry OT_OP_GRAD_POS
-    bool small_table;         // tiles of at most kSmallTile points: the small spreading table
-    uint64_t *skv[2];         // host's leaf entry << 32 | input index, in sorted order
-    void *srec[2];            // position (+ force) records in sorted order
-    void *sws;                // counting workspace
-};
 
 namespace ot {
-namespace {
 
-constexpr uint32_t kCountMask = 0x00FFFFFFu;
-
-
-// GRAD: the plan's ops are gradient passes (8, 10, 12), else forward (1..7).
-// S: slots of the workgroup's spreading table.
-template <typename T, int MODE, bool PER, bool GRAD, int S>
-__global__ __launch_bounds__(512) void k_batch(TreeView tv, const int64_t *__restrict__ tile_start,
-                                               const uint32_t *__restrict__ tile_info, int64_t n_tiles,
-                                               unsigned *__restrict__ counter, const uint64_t *__restrict__ kv,
-                                               int rs, const T *__restrict__ pos,
-                                               const T *__restrict__ field, const T *__restrict__ force,
-                                               int32_t *__restrict__ ids, T *__restrict__ vel, T *__restrict__ fout,
-                                               unsigned long long *__restrict__ facc, const FxState *__restrict__ fx,
-                                               T *__restrict__ grad)
-{
-    using Acc = typename AccType<T, MODE>::type;
-    __shared__ uint32_t keys[S];
-    __shared__ Acc vals[LdsSink<T, MODE, S>::kVals];
-    __shared__ unsigned s_tile;
-    const double scale = MODE == kModeFixed ? fx->scale : 0.0;
-    LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
-    sink.clear();
-    // The next tile is claimed before the flush, so the queue atomic's round
-    // trip overlaps it.  Every thread reads s_tile before the flush's first
-    // barrier, and thread 0 writes it again only after the flush's last one.
-    unsigned nxt = 0u;
-    if (threadIdx.x == 0) nxt = atomicAdd(counter, 1u);
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = nxt;
-        __syncthreads();
-        const int64_t tile = s_tile;
-        if (tile >= n_tiles) break;   // same value in every thread of the workgroup
-        const int64_t start = tile_start[tile];
-        const uint32_t info = tile_info[tile];
-        const int64_t end = start + (int64_t)(info & kCountMask);
-        if constexpr (!GRAD) {
-            switch (info >> 24) {
-#define OT_CASE(OPSV) \
-    case OPSV: track_range<T, OPSV, PER>(tv, start, end, kv, rs, pos, field, force, ids, vel, sink); break;
-                OT_CASE(1) OT_CASE(2) OT_CASE(3) OT_CASE(4) OT_CASE(5) OT_CASE(6) OT_CASE(7)
-#undef OT_CASE
-            default: break;
-            }
-        } else {
-            switch (info >> 24) {
-#define OT_CASE(OPSV) \
-    case OPSV: track_range<T, OPSV, PER>(tv, start, end, kv, rs, pos, field, force, ids, vel, sink, grad); break;
-                OT_CASE(kOpGrad) OT_CASE(kOpGrad | kOpInterp) OT_CASE(kOpGrad | kOpSpread)
-#undef OT_CASE
-            default: break;
-            }
-        }
-        if (threadIdx.x == 0) nxt = atomicAdd(counter, 1u);
-        sink.flush();   // one spatially coherent tile per table fill
-    }
-}
-
+// Instantiated in batch_inst.hip (batch_kernels.h).
 template <typename T, int MODE>
 int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids, void *vel,
-            void *fout, void *grad, hipStream_t s)
-{
-    const ot_tree *t = p->tree;
-    const int64_t n = p->n_points;
-    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, p->counter, (int64_t)1, 0u);
-    int rc;
-    const bool spread = (p->ops_union & kOpSpread) != 0;
-    if (spread && (rc = spread_begin(t, p->dtype, p->mode, 0, fout, s))) return rc;
-    const uint64_t *kv = nullptr;
-    int rs = 3;
-    int32_t *kids = ids;
-    const T *kpos = (const T *)pos, *kforce = (const T *)force;
-    const void *scale_from = force;   // max |F| still to take (FIXED)
-    if (p->sort_points && n > 0) {
-        // ids come from the key pass; positions and forces travel with the
-        // keys, and the first pass takes max |F| on the way
-        const bool carry_force = (p->ops_all & (kOpSpread | kOpGrad)) != 0;
-        PointSortBufs<T> b{{p->skv[0], p->skv[1]}, {(T *)p->srec[0], (T *)p->srec[1]}, p->sws};
-        PointSortResult<T> r;
-        unsigned long long *maxbits = ((p->ops_all & kOpSpread) && p->mode == OT_SPREAD_FIXED)
-                                          ? &((FxState *)t->scratch)->maxbits
-                                          : nullptr;
-        point_sort<T>(t->view, n, t->n_leaves, p->sort_shift, p->sort_bits, (const T *)pos,
-                      carry_force ? (const T *)force : nullptr, (p->ops_all & kOpLocate) ? ids : nullptr, b, maxbits,
-                      s, r);
-        kv = r.kv;
-        rs = r.stride;
-        kpos = r.rec;
-        kforce = carry_force ? r.rec + 3 : nullptr;
-        kids = nullptr;
-        if (maxbits) scale_from = nullptr;
-    }
-    if (spread && (rc = spread_scale(t, p->dtype, p->mode, scale_from, n, s))) return rc;
-    if (p->timing) OT_HIP(hipEventRecord(p->ev[0], s));
-#define OT_KBATCH_S(PERV, GRADV, SV)                                                                               \
-    hipLaunchKernelGGL((k_batch<T, MODE, PERV, GRADV, SV>), dim3(p->grid), dim3(p->block), 0, s, t->view,            \
-                       p->tile_start, p->tile_info, p->n_tiles, p->counter, kv, rs, kpos, (const T *)field, kforce,  \
-                       kids, (T *)vel, (T *)fout, t->fx_acc, (const FxState *)t->scratch, (T *)grad)
-#define OT_KBATCH(PERV, GRADV)                                                                                     \
-    do {                                                                                                           \
-        if (p->small_table) OT_KBATCH_S(PERV, GRADV, kSmallSlots);                                                \
-        else OT_KBATCH_S(PERV, GRADV, (SinkSlots<T, MODE>::value));                                                \
-    } while (0)
-    if (p->grad_plan) {
-        if (t->view.periodic) OT_KBATCH(true, true);
-        else OT_KBATCH(false, true);
-    } else {
-        if (t->view.periodic) OT_KBATCH(true, false);
-        else OT_KBATCH(false, false);
-    }
-#undef OT_KBATCH
-#undef OT_KBATCH_S
-    OT_HIP(hipGetLastError());
-    if (p->timing) OT_HIP(hipEventRecord(p->ev[1], s));
-    if (p->ops_union & kOpSpread)
-        if ((rc = spread_epilogue(t, p->dtype, p->mode, 0, fout, s))) return rc;
-    OT_HIP(hipGetLastError());
-    return OT_OK;
-}
+            void *fout, void *grad, hipStream_t s);
+template <typename T, int MODE>
+const void *kbatch_fn(bool grad, bool small);
+template <typename T, int MODE>
+const void *hm_fn(int ops);
+constexpr int kHmWindow = 256;   // points per window of the host-major pass (kHmThreads)
+
+namespace {
 
 int enqueue_any(ot_batch_plan *p, const void *field, const void *force, const void *pos, int32_t *ids, void *vel,
                 void *fout, void *grad, hipStream_t s)
@@ -179,15 +40,6 @@ int enqueue_any(ot_batch_plan *p, const void *field, const void *force, const vo
                                           : enqueue<float, kModeAtomic>(p, field, force, pos, ids, vel, fout, grad, s);
     return p->mode == OT_SPREAD_FIXED ? enqueue<double, kModeFixed>(p, field, force, pos, ids, vel, fout, grad, s)
                                       : enqueue<double, kModeAtomic>(p, field, force, pos, ids, vel, fout, grad, s);
-}
-
-// The persistent kernel of a plan (for the occupancy query).
-template <typename T, int MODE>
-const void *kbatch_fn(bool grad, bool small)
-{
-    constexpr int L = SinkSlots<T, MODE>::value;
-    if (grad) return small ? (const void *)k_batch<T, MODE, true, true, kSmallSlots> : (const void *)k_batch<T, MODE, true, true, L>;
-    return small ? (const void *)k_batch<T, MODE, true, false, kSmallSlots> : (const void *)k_batch<T, MODE, true, false, L>;
 }
 
 bool valid_ops(int o)
@@ -245,6 +97,10 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     int ops_union = 0, ops_all = -1;
     for (int i = 0; i < n_inst; ++i) {
         if (offsets[i + 1] < offsets[i]) return fail(OT_ERR_INVALID, "offsets must be ascending");
+        // the sorted pass covers every point of the run with the common ops,
+        // so it cannot leave an instance's points untouched
+        if (sort_points && ops[i] == 0 && offsets[i + 1] > offsets[i])
+            return fail(OT_ERR_INVALID, "point sorting cannot skip an instance (ops = 0 with points)");
         if (ops[i] == 0 || offsets[i + 1] == offsets[i]) continue;
         ops_union |= ops[i];
         if (ops_all >= 0 && ops_all != ops[i] && sort_points)
@@ -298,6 +154,26 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
             return fail(OT_ERR_OOM, "ot_batch_plan_create: sort buffers");
         }
     }
+    // sorted forward plans that interpolate or spread take the host-major pass
+    p->use_hm = sort_points && !p->grad_plan && (ops_all & (kOpInterp | kOpSpread)) != 0 &&
+                !(tuning && (tuning->flags & OT_TUNE_PER_POINT)) && p->n_points > 0;
+    if (p->use_hm) {
+        p->n_win = (p->n_points + kHmWindow - 1) / kHmWindow;
+        if (hipMalloc((void **)&p->fb_list, (size_t)p->n_win * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            p->fb_list = nullptr;
+            ot_batch_plan_destroy(p);
+            return fail(OT_ERR_OOM, "ot_batch_plan_create: window list");
+        }
+    }
+    if (mode == OT_SPREAD_FIXED && (ops_union & kOpSpread)) {
+        if (hipMalloc(&p->fxws, (size_t)spread_ws_bytes(tree->n_leaves)) != hipSuccess) {
+            (void)hipGetLastError();
+            p->fxws = nullptr;
+            ot_batch_plan_destroy(p);
+            return fail(OT_ERR_OOM, "ot_batch_plan_create: fixed-point workspace");
+        }
+    }
     int cus = 0, dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -313,6 +189,18 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     int grid = tuning && tuning->grid ? tuning->grid : std::max(1, cus) * per_cu;
     if (p->n_tiles > 0 && grid > p->n_tiles) grid = (int)p->n_tiles;
     p->grid = std::max(1, grid);
+    if (p->use_hm) {
+        const int hops = ops_all & (kOpInterp | kOpSpread);
+        const void *hfn = dtype == OT_F32 ? (mode == OT_SPREAD_FIXED ? hm_fn<float, kModeFixed>(hops)
+                                                                     : hm_fn<float, kModeAtomic>(hops))
+                                          : (mode == OT_SPREAD_FIXED ? hm_fn<double, kModeFixed>(hops)
+                                                                     : hm_fn<double, kModeAtomic>(hops));
+        int hper = 0;
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&hper, hfn, kHmWindow, 0);
+        if (hper <= 0) hper = 1;
+        int hg = tuning && tuning->grid ? tuning->grid : std::max(1, cus) * hper;
+        p->hm_grid = (int)std::max<int64_t>(1, std::min<int64_t>(hg, p->n_win));
+    }
     hipError_t e1 = hipMalloc((void **)&p->tile_start, std::max<size_t>(8, starts.size() * 8));
     hipError_t e2 = hipMalloc((void **)&p->tile_info, std::max<size_t>(4, infos.size() * 4));
     hipError_t e3 = hipMalloc((void **)&p->counter, 64);
@@ -432,6 +320,22 @@ extern "C" int ot_batch_last_kernel_ms(const ot_batch_plan *p, float *ms)
     return OT_OK;
 }
 
+extern "C" int ot_batch_plan_windows(const ot_batch_plan *p, int64_t *n_windows, int64_t *handed_over)
+{
+    if (!p) return fail(OT_ERR_INVALID, "plan is NULL");
+    const int64_t nw = p->use_hm ? p->n_win : 0;
+    if (n_windows) *n_windows = nw;
+    if (handed_over) {
+        *handed_over = 0;
+        if (nw > 0) {
+            unsigned c = 0;
+            OT_HIP(hipMemcpy(&c, p->counter + 2, sizeof(c), hipMemcpyDeviceToHost));
+            *handed_over = c;
+        }
+    }
+    return OT_OK;
+}
+
 extern "C" int ot_batch_plan_destroy(ot_batch_plan *p)
 {
     if (!p) return OT_OK;
@@ -439,7 +343,7 @@ extern "C" int ot_batch_plan_destroy(ot_batch_plan *p)
     drop_graph(p);
     if (p->ev[0]) (void)hipEventDestroy(p->ev[0]);
     if (p->ev[1]) (void)hipEventDestroy(p->ev[1]);
-    for (void *q : {(void *)p->skv[0], (void *)p->skv[1], p->srec[0], p->srec[1], p->sws})
+    for (void *q : {(void *)p->skv[0], (void *)p->skv[1], p->srec[0], p->srec[1], p->sws, p->fxws, (void *)p->fb_list})
         if (q) (void)hipFree(q);
     if (p->tile_start) (void)hipFree(p->tile_start);
     if (p->tile_info) (void)hipFree(p->tile_info);

@@ -34,10 +34,11 @@ constexpr int64_t kMaxLeaves = int64_t(1) << 26;
 
 struct TreeView {
     const uint32_t *table;
+    const uint8_t *levels;   // leaf levels in id order (hosts given by id)
     int32_t L;         // finest level
     int32_t periodic;
     int32_t nlev;      // table levels (root included)
-    int32_t pad;
+    int32_t nleaf;     // leaves (ids are 0 .. nleaf - 1)
     int32_t lev[kMaxTabLevels];   // cell level of each table level; lev[0] = root level
     int64_t off[kMaxTabLevels];   // entry offset of each level's pool; off[0] = 0
 };
@@ -197,6 +198,11 @@ int64_t radix_ws_bytes(int64_t n);
 void radix_sort_pairs(uint64_t *k0, int32_t *v0, uint64_t *k1, int32_t *v1, int64_t n, int bits, void *ws,
                       uint64_t **k_res, int32_t **v_res, hipStream_t s);
 int fail(int code, const std::string &msg);
+
+// Fixed-point spreading workspace: a 256-byte header (FxState) followed by
+// the n_leaves x 3 int64 accumulators.
+constexpr int64_t kFxHeader = 256;
+inline int64_t spread_ws_bytes(int64_t n_leaves) { return kFxHeader + n_leaves * 3 * 8; }
 int hip_fail(hipError_t e, const char *what);
 
 #define OT_HIP(call)                                      \
@@ -217,6 +223,7 @@ struct ot_tree {
     uint32_t *table;     // descent table (root + pools)
     int64_t table_entries;
     ot::TreeView view;
-    unsigned long long *fx_acc;   // fixed-point accumulators, n_leaves * 3
-    unsigned int *scratch;        // small device scratch (reductions)
+    // Read-only after the build: the workspace of fixed-point spreading
+    // belongs to each call (or batch plan), so calls on one tree may run on
+    // several streams at once.
 };

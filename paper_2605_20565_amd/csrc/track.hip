@@ -14,143 +14,77 @@
 
 namespace ot {
 
-namespace {
-
-// One workgroup per tile of `tile` consecutive points.  Spreading goes
-// through the workgroup's LDS aggregation table of S slots, flushed once at
-// the end.
-template <typename T, int OPS, int MODE, bool PER, int S>
-__global__ __launch_bounds__(512) void k_track(TreeView tv, int64_t n, int64_t tile, const T *__restrict__ pos,
-                                               const T *__restrict__ field, const T *__restrict__ force,
-                                               int32_t *__restrict__ ids, T *__restrict__ vel,
-                                               T *__restrict__ fout, unsigned long long *__restrict__ facc,
-                                               const FxState *__restrict__ fx, T *__restrict__ grad)
-{
-    const int64_t start = (int64_t)blockIdx.x * tile;
-    const int64_t end = start + tile < n ? start + tile : n;
-    if constexpr ((OPS & kOpSpread) != 0) {
-        using Acc = typename AccType<T, MODE>::type;
-        __shared__ uint32_t keys[S];
-        __shared__ Acc vals[LdsSink<T, MODE, S>::kVals];
-        const double scale = MODE == kModeFixed ? fx->scale : 0.0;
-        LdsSink<T, MODE, S> sink{keys, vals, fout, facc, scale};
-        sink.clear();
-        __syncthreads();
-        track_range<T, OPS, PER>(tv, start, end, nullptr, 3, pos, field, force, ids, vel, sink, grad);
-        sink.flush();
-    } else {
-        DirectSink<T, MODE> sink{fout, facc, 0.0};
-        track_range<T, OPS, PER>(tv, start, end, nullptr, 3, pos, field, force, ids, vel, sink, grad);
-    }
-}
+// Launch of the plain kernels for one (precision, mode); instantiated in
+// track_inst.hip (track_kernels.h).
+template <typename T, int MODE>
+int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStream_t s, int64_t n, const void *pos,
+                 const void *field, const void *force, int32_t *ids, void *vel, void *fout, void *grad,
+                 const FxWs &ws, const int32_t *hid);
 
 constexpr int kMaxPointsPerThread = 4;
 
-template <typename T, int OPS, int MODE, int S>
-void launch_track(const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStream_t s, int64_t n, const T *P, const T *Fd,
-                  const T *Fo, int32_t *ids, T *V, T *O, const FxState *fx, T *Gr)
-{
-    if (t->view.periodic)
-        hipLaunchKernelGGL((k_track<T, OPS, MODE, true, S>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,
-                           t->fx_acc, fx, Gr);
-    else
-        hipLaunchKernelGGL((k_track<T, OPS, MODE, false, S>), g, b, 0, s, t->view, n, tile, P, Fd, Fo, ids, V, O,
-                           t->fx_acc, fx, Gr);
-}
-
-template <typename T, int MODE>
-int dispatch_ops(int ops, const ot_tree *t, dim3 g, dim3 b, int64_t tile, hipStream_t s, int64_t n, const void *pos,
-                 const void *field, const void *force, int32_t *ids, void *vel, void *fout, void *grad)
-{
-    const T *P = (const T *)pos, *Fd = (const T *)field, *Fo = (const T *)force;
-    T *V = (T *)vel, *O = (T *)fout, *Gr = (T *)grad;
-    const FxState *fx = (const FxState *)t->scratch;
-    constexpr int kSlots = SinkSlots<T, MODE>::value;
-    const bool small = tile <= kSmallTile;
-#define OT_LAUNCH(OPSV)                                                                                          \
-    if (small)                                                                                                   \
-        launch_track<T, OPSV, MODE, ((OPSV) & kOpSpread) ? kSmallSlots : kSlots>(t, g, b, tile, s, n, P, Fd, Fo,  \
-                                                                                ids, V, O, fx, Gr);               \
-    else                                                                                                         \
-        launch_track<T, OPSV, MODE, kSlots>(t, g, b, tile, s, n, P, Fd, Fo, ids, V, O, fx, Gr);                   \
-    break;
-    switch (ops) {
-    case 1: OT_LAUNCH(1)
-    case 2: OT_LAUNCH(2)
-    case 3: OT_LAUNCH(3)
-    case 4: OT_LAUNCH(4)
-    case 5: OT_LAUNCH(5)
-    case 6: OT_LAUNCH(6)
-    case 7: OT_LAUNCH(7)
-    // gradient passes: alone, with the interpolation (backward of spreading)
-    // or with the spreading (backward of interpolation)
-    case kOpGrad: OT_LAUNCH(kOpGrad)
-    case kOpGrad | kOpInterp: OT_LAUNCH(kOpGrad | kOpInterp)
-    case kOpGrad | kOpSpread: OT_LAUNCH(kOpGrad | kOpSpread)
-    default: return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
-    }
-#undef OT_LAUNCH
-    return OT_OK;
-}
-
-}  // namespace
-
 // Prepare the spreading target before a pass: zero the output (atomic mode,
 // overwrite) or the fixed-point accumulators and compute the scale.
-int spread_begin(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s)
+int spread_begin(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s)
 {
     const int64_t n3 = t->n_leaves * 3;
-    FxState *fx = (FxState *)t->scratch;
     if (mode == OT_SPREAD_ATOMIC) {
         if (!accumulate) {
             if (dtype == OT_F32) hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, (float *)fout, n3, 0.0f);
             else hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, (double *)fout, n3, 0.0);
         }
     } else {
-        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1024), dim3(256), 0, s, t->fx_acc, n3, 0ull);
-        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &fx->maxbits, (int64_t)1, 0ull);
+        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1024), dim3(256), 0, s, ws.acc, n3, 0ull);
+        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &ws.fx->maxbits, (int64_t)1, 0ull);
     }
     OT_HIP(hipGetLastError());
     return OT_OK;
 }
 
-int spread_scale(const ot_tree *t, int dtype, int mode, const void *force, int64_t n, hipStream_t s)
+int spread_scale(const ot_tree *t, const FxWs &ws, int dtype, int mode, const void *force, int64_t n, hipStream_t s)
 {
+    (void)t;
     if (mode != OT_SPREAD_FIXED) return OT_OK;
-    FxState *fx = (FxState *)t->scratch;
     const int64_t m = force ? n * 3 : 0;
     if (m > 0) {
         unsigned gb = (unsigned)std::min<int64_t>((m + 1023) / 1024, 1024);
         if (dtype == OT_F32)
-            hipLaunchKernelGGL(k_maxabs<float>, dim3(gb), dim3(256), 0, s, (const float *)force, m, &fx->maxbits);
+            hipLaunchKernelGGL(k_maxabs<float>, dim3(gb), dim3(256), 0, s, (const float *)force, m, &ws.fx->maxbits);
         else
-            hipLaunchKernelGGL(k_maxabs<double>, dim3(gb), dim3(256), 0, s, (const double *)force, m, &fx->maxbits);
+            hipLaunchKernelGGL(k_maxabs<double>, dim3(gb), dim3(256), 0, s, (const double *)force, m, &ws.fx->maxbits);
     }
-    if (dtype == OT_F32) hipLaunchKernelGGL(k_fx_prepare<float>, dim3(1), dim3(64), 0, s, fx, n);
-    else hipLaunchKernelGGL(k_fx_prepare<double>, dim3(1), dim3(64), 0, s, fx, n);
+    if (dtype == OT_F32) hipLaunchKernelGGL(k_fx_prepare<float>, dim3(1), dim3(64), 0, s, ws.fx, n);
+    else hipLaunchKernelGGL(k_fx_prepare<double>, dim3(1), dim3(64), 0, s, ws.fx, n);
     OT_HIP(hipGetLastError());
     return OT_OK;
 }
 
-int spread_prologue(const ot_tree *t, int dtype, int mode, int accumulate, const void *force, int64_t n,
-                    void *fout, hipStream_t s)
+int spread_prologue(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, const void *force,
+                    int64_t n, void *fout, hipStream_t s)
 {
-    int rc = spread_begin(t, dtype, mode, accumulate, fout, s);
-    return rc ? rc : spread_scale(t, dtype, mode, force, n, s);
+    int rc = spread_begin(t, ws, dtype, mode, accumulate, fout, s);
+    return rc ? rc : spread_scale(t, ws, dtype, mode, force, n, s);
 }
 
-int spread_epilogue(const ot_tree *t, int dtype, int mode, int accumulate, void *fout, hipStream_t s)
+int spread_epilogue(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s)
 {
     if (mode != OT_SPREAD_FIXED) return OT_OK;
     const int64_t n3 = t->n_leaves * 3;
-    const FxState *fx = (const FxState *)t->scratch;
     const unsigned gb = (unsigned)std::min<int64_t>((n3 + 255) / 256, 8192);
     if (dtype == OT_F32)
-        hipLaunchKernelGGL(k_fx_finalize<float>, dim3(gb), dim3(256), 0, s, t->fx_acc, (float *)fout, n3, fx, accumulate);
+        hipLaunchKernelGGL(k_fx_finalize<float>, dim3(gb), dim3(256), 0, s, ws.acc, (float *)fout, n3, ws.fx, accumulate);
     else
-        hipLaunchKernelGGL(k_fx_finalize<double>, dim3(gb), dim3(256), 0, s, t->fx_acc, (double *)fout, n3, fx, accumulate);
+        hipLaunchKernelGGL(k_fx_finalize<double>, dim3(gb), dim3(256), 0, s, ws.acc, (double *)fout, n3, ws.fx, accumulate);
     OT_HIP(hipGetLastError());
     return OT_OK;
+}
+
+FxWs fx_ws(void *work)
+{
+    FxWs w;
+    w.fx = (FxState *)work;
+    w.acc = work ? (unsigned long long *)((char *)work + kFxHeader) : nullptr;
+    return w;
 }
 
 int check_common(const ot_tree *t, int dtype, int64_t n, const void *pos)
@@ -167,7 +101,8 @@ namespace {
 
 // The pass's kernel alone, no clearing, scale or conversion around it.
 int launch_ops(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
-               int mode, int32_t *ids, void *vel, void *fout, void *grad, hipStream_t s)
+               int mode, int32_t *ids, void *vel, void *fout, void *grad, const FxWs &ws, const int32_t *hid,
+               hipStream_t s)
 {
     int rc = OT_OK;
     if (n > 0) {
@@ -183,12 +118,16 @@ int launch_ops(const ot_tree *t, int ops, const void *field, const void *force, 
         dim3 b(threads), g((unsigned)((n + tile - 1) / tile));
         if (dtype == OT_F32)
             rc = mode == OT_SPREAD_FIXED
-                     ? dispatch_ops<float, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad)
-                     : dispatch_ops<float, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad);
+                     ? dispatch_ops<float, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad,
+                                                       ws, hid)
+                     : dispatch_ops<float, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout,
+                                                        grad, ws, hid);
         else
             rc = mode == OT_SPREAD_FIXED
-                     ? dispatch_ops<double, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad)
-                     : dispatch_ops<double, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout, grad);
+                     ? dispatch_ops<double, kModeFixed>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout,
+                                                        grad, ws, hid)
+                     : dispatch_ops<double, kModeAtomic>(ops, t, g, b, tile, s, n, pos, field, force, ids, vel, fout,
+                                                         grad, ws, hid);
         if (rc) return rc;
         OT_HIP(hipGetLastError());
     }
@@ -196,9 +135,12 @@ int launch_ops(const ot_tree *t, int ops, const void *field, const void *force, 
 }
 
 // One pass over the points with the ops in `ops` (OT_OP_* bits, or the
-// gradient with at most one of interpolation and spreading).
+// gradient with at most one of interpolation and spreading).  hid: the
+// caller's host ids (nullable).  work: the fixed-point spreading workspace
+// (FIXED spreading only; NULL: allocated on the stream for this call).
 int run_pass(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
-             int mode, int accumulate, int32_t *ids, void *vel, void *fout, void *grad, hipStream_t s)
+             int mode, int accumulate, int32_t *ids, void *vel, void *fout, void *grad, const int32_t *hid,
+             void *work, hipStream_t s)
 {
     int rc = check_common(t, dtype, n, pos);
     if (rc) return rc;
@@ -209,66 +151,91 @@ int run_pass(const ot_tree *t, int ops, const void *field, const void *force, co
     if ((ops & kOpInterp) && ((n > 0 && !vel) || !field)) return fail(OT_ERR_INVALID, "field or vel is NULL");
     if ((ops & kOpGrad) && ((n > 0 && (!grad || !force)) || !field))
         return fail(OT_ERR_INVALID, "field, vector or gradient output is NULL");
-    if (ops & kOpSpread) {
+    const bool spread = (ops & kOpSpread) != 0;
+    if (spread) {
         if ((n > 0 && !force) || !fout) return fail(OT_ERR_INVALID, "force or field_out is NULL");
         if (mode != OT_SPREAD_ATOMIC && mode != OT_SPREAD_FIXED) return fail(OT_ERR_INVALID, "bad spread mode");
-        if ((rc = spread_prologue(t, dtype, mode, accumulate, force, n, fout, s))) return rc;
     }
-    if ((rc = launch_ops(t, ops, field, force, pos, dtype, n, mode, ids, vel, fout, grad, s))) return rc;
-    if (ops & kOpSpread) return spread_epilogue(t, dtype, mode, accumulate, fout, s);
-    return OT_OK;
+    if (work && ((uintptr_t)work & 255u)) return fail(OT_ERR_INVALID, "work must be 256-byte aligned");
+    void *owned = nullptr;
+    if (spread && mode == OT_SPREAD_FIXED && !work) {
+        hipError_t e = hipMallocAsync(&owned, (size_t)spread_ws_bytes(t->n_leaves), s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(OT_ERR_OOM, "fixed-point spreading workspace");
+        }
+        work = owned;
+    }
+    const FxWs ws = fx_ws(work);
+    if (spread) rc = spread_prologue(t, ws, dtype, mode, accumulate, force, n, fout, s);
+    if (!rc) rc = launch_ops(t, ops, field, force, pos, dtype, n, mode, ids, vel, fout, grad, ws, hid, s);
+    if (!rc && spread) rc = spread_epilogue(t, ws, dtype, mode, accumulate, fout, s);
+    if (owned) (void)hipFreeAsync(owned, s);
+    return rc;
 }
 
 }  // namespace
-
-int track(const ot_tree *t, int ops, const void *field, const void *force, const void *pos, int dtype, int64_t n,
-          int mode, int accumulate, int32_t *ids, void *vel, void *fout, hipStream_t s)
-{
-    if (ops <= 0 || ops > 7) return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
-    return run_pass(t, ops, field, force, pos, dtype, n, mode, accumulate, ids, vel, fout, nullptr, s);
-}
 
 }  // namespace ot
 
 using namespace ot;
 
+extern "C" int64_t ot_spread_workspace_bytes(const ot_tree *t)
+{
+    return t ? spread_ws_bytes(t->n_leaves) : 0;
+}
+
 extern "C" int ot_locate(const ot_tree *t, const void *pos, int32_t dtype, int64_t n, int32_t *ids, void *stream)
 {
-    return track(t, kOpLocate, nullptr, nullptr, pos, dtype, n, OT_SPREAD_ATOMIC, 0, ids, nullptr, nullptr,
-                 (hipStream_t)stream);
+    return run_pass(t, kOpLocate, nullptr, nullptr, pos, dtype, n, OT_SPREAD_ATOMIC, 0, ids, nullptr, nullptr, nullptr,
+                    nullptr, nullptr, (hipStream_t)stream);
 }
 
-extern "C" int ot_interpolate(const ot_tree *t, const void *field, const void *pos, int32_t dtype, int64_t n,
-                              void *vel, void *stream)
+extern "C" int ot_interpolate(const ot_tree *t, const void *field, const void *pos, const int32_t *ids,
+                              int32_t dtype, int64_t n, void *vel, void *stream)
 {
-    return track(t, kOpInterp, field, nullptr, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, vel, nullptr,
-                 (hipStream_t)stream);
+    return run_pass(t, kOpInterp, field, nullptr, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, vel, nullptr, nullptr,
+                    ids, nullptr, (hipStream_t)stream);
 }
 
-extern "C" int ot_spread(const ot_tree *t, const void *force, const void *pos, int32_t dtype, int64_t n, int32_t mode,
-                         int32_t accumulate, void *field_out, void *stream)
+extern "C" int ot_spread(const ot_tree *t, const void *force, const void *pos, const int32_t *ids, int32_t dtype,
+                         int64_t n, int32_t mode, int32_t accumulate, void *field_out, void *work, void *stream)
 {
-    return track(t, kOpSpread, nullptr, force, pos, dtype, n, mode, accumulate, nullptr, nullptr, field_out,
-                 (hipStream_t)stream);
+    return run_pass(t, kOpSpread, nullptr, force, pos, dtype, n, mode, accumulate, nullptr, nullptr, field_out,
+                    nullptr, ids, work, (hipStream_t)stream);
 }
 
 extern "C" int ot_track(const ot_tree *t, int32_t ops, const void *field, const void *force, const void *pos,
                         int32_t dtype, int64_t n, int32_t mode, int32_t accumulate, int32_t *ids, void *vel,
-                        void *field_out, void *stream)
+                        void *field_out, void *work, void *stream)
 {
-    return track(t, ops, field, force, pos, dtype, n, mode, accumulate, ids, vel, field_out, (hipStream_t)stream);
-}
-
-extern "C" int ot_grad_pos(const ot_tree *t, const void *field, const void *vec, const void *pos, int32_t dtype,
-                           int64_t n, void *grad, void *stream)
-{
-    return run_pass(t, kOpGrad, field, vec, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, nullptr, nullptr, grad,
+    if (ops <= 0 || ops > 7) return fail(OT_ERR_INVALID, "ops must be a non-empty combination of OT_OP_* bits");
+    return run_pass(t, ops, field, force, pos, dtype, n, mode, accumulate, ids, vel, field_out, nullptr, nullptr, work,
                     (hipStream_t)stream);
 }
 
+extern "C" int ot_grad_pos(const ot_tree *t, const void *field, const void *vec, const void *pos, const int32_t *ids,
+                           int32_t dtype, int64_t n, void *grad, void *stream)
+{
+    return run_pass(t, kOpGrad, field, vec, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, nullptr, nullptr, grad, ids,
+                    nullptr, (hipStream_t)stream);
+}
+
+extern "C" int ot_interp_grad_pos(const ot_tree *t, const void *field, const void *grad_vel, const void *pos,
+                                  const int32_t *ids, int32_t dtype, int64_t n, void *grad_pos, void *stream)
+{
+    return ot_grad_pos(t, field, grad_vel, pos, ids, dtype, n, grad_pos, stream);
+}
+
+extern "C" int ot_spread_grad_pos(const ot_tree *t, const void *grad_field, const void *force, const void *pos,
+                                  const int32_t *ids, int32_t dtype, int64_t n, void *grad_pos, void *stream)
+{
+    return ot_grad_pos(t, grad_field, force, pos, ids, dtype, n, grad_pos, stream);
+}
+
 extern "C" int ot_interp_backward(const ot_tree *t, const void *field, const void *grad_vel, const void *pos,
-                                  int32_t dtype, int64_t n, int32_t mode, int32_t accumulate, void *grad_field,
-                                  void *grad_pos, void *stream)
+                                  const int32_t *ids, int32_t dtype, int64_t n, int32_t mode, int32_t accumulate,
+                                  void *grad_field, void *grad_pos, void *work, void *stream)
 {
     int ops = (grad_field ? (int)kOpSpread : 0) | (grad_pos ? (int)kOpGrad : 0);
     if (n == 0) ops &= ~(int)kOpGrad;   // no points: no position gradient (grad_field is still cleared)
@@ -277,15 +244,16 @@ extern "C" int ot_interp_backward(const ot_tree *t, const void *field, const voi
         return fail(OT_ERR_INVALID, "ot_interp_backward: both outputs are NULL");
     }
     return run_pass(t, ops, field, grad_vel, pos, dtype, n, mode, accumulate, nullptr, nullptr, grad_field, grad_pos,
-                    (hipStream_t)stream);
+                    ids, work, (hipStream_t)stream);
 }
 
 extern "C" int ot_spread_backward(const ot_tree *t, const void *grad_field, const void *force, const void *pos,
-                                  int32_t dtype, int64_t n, void *grad_force, void *grad_pos, void *stream)
+                                  const int32_t *ids, int32_t dtype, int64_t n, void *grad_force, void *grad_pos,
+                                  void *stream)
 {
     const int ops = (grad_force ? (int)kOpInterp : 0) | (grad_pos ? (int)kOpGrad : 0);
     if (n == 0) return check_common(t, dtype, n, pos);   // both outputs are per point: nothing to do
     if (!ops) return fail(OT_ERR_INVALID, "ot_spread_backward: both outputs are NULL");
     return run_pass(t, ops, grad_field, force, pos, dtype, n, OT_SPREAD_ATOMIC, 0, nullptr, grad_force, nullptr,
-                    grad_pos, (hipStream_t)stream);
+                    grad_pos, ids, nullptr, (hipStream_t)stream);
 }

@@ -16,12 +16,19 @@ enum : int { kOpLocate = OT_OP_LOCATE, kOpInterp = OT_OP_INTERPOLATE, kOpSpread 
 enum : int { kOpGrad = OT_OP_GRAD_POS };
 enum : int { kModeAtomic = OT_SPREAD_ATOMIC, kModeFixed = OT_SPREAD_FIXED };
 
-// Fixed-point spreading state (lives in the tree's scratch buffer).
+// Fixed-point spreading state: the header of a spreading workspace (the
+// caller's, or a batch plan's).
 struct FxState {
     unsigned long long maxbits;   // bit pattern of max |F| (IEEE order == value order for >= 0)
     double scale;                 // 2^s
     double inv;                   // 2^-s
     unsigned long long pad;
+};
+
+// A spreading workspace: header and n_leaves x 3 int64 accumulators.
+struct FxWs {
+    unsigned long long *acc;
+    FxState *fx;
 };
 
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
@@ -280,25 +287,41 @@ struct LdsSink {
     }
 };
 
+// Table entry (level << 26 | id) of a host given by its leaf id; ids
+// outside [0, n_leaves) give no host.
+__device__ __forceinline__ bool host_from_id(const TreeView &tv, int32_t h, uint32_t &e)
+{
+    const bool ok = h >= 0 && h < tv.nleaf;
+    e = ok ? (((uint32_t)tv.levels[h] << kLevelShift) | (uint32_t)h) : 0u;
+    return ok;
+}
+
 // Point k: position X (loaded by the caller from pos[rs k + 0..2]), force
 // force[rs k + 0..2] (rs = 3 for the caller's arrays, the record stride for
 // sorted records).  For sorted points, word is the point's sort word (the
 // host's leaf entry << 32 | input index): the host comes from the word,
 // found by the sort's key pass on the same position, and the per-point
-// outputs go to the input index.  With kOpGrad, force[k] is also
-// the vector the gradient contracts the field with, and the gradient goes
-// to grad.
+// outputs go to the input index.  Otherwise the host is hid[k] when the
+// caller gives host ids (Algorithm 1's host_cell_id; -1 or an id out of
+// range: no host), else the table descent finds it.  With kOpGrad, force[k]
+// is also the vector the gradient contracts the field with, and the
+// gradient goes to grad.
 template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bool sorted, uint64_t word,
                                                const T (&X)[3], int rs, const T *__restrict__ field,
                                                const T *__restrict__ force, int32_t *__restrict__ ids,
-                                               T *__restrict__ vel, Sink &sink, T *__restrict__ grad)
+                                               T *__restrict__ vel, Sink &sink, T *__restrict__ grad,
+                                               const int32_t *__restrict__ hid)
 {
     const int64_t kd = sorted ? (int64_t)(uint32_t)word : k;
     const int64_t kp = (int64_t)rs * k;
     uint32_t I[3];
-    const bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
-    const uint32_t e = ok ? (sorted ? (uint32_t)(word >> 32) : descend(tv, I[0], I[1], I[2])) : 0u;
+    bool ok = point_cell<T>(tv, X[0], X[1], X[2], I);
+    uint32_t e = 0u;
+    if (sorted) e = (uint32_t)(word >> 32);
+    else if (hid) ok = host_from_id(tv, hid[k], e) && ok;
+    else if (ok) e = descend(tv, I[0], I[1], I[2]);
+    if (!ok) e = 0u;
     if (OPS & kOpLocate) ids[kd] = ok ? (int32_t)(e & kIdMask) : -1;
     if (!(OPS & (kOpInterp | kOpSpread | kOpGrad))) return;
 
@@ -488,12 +511,13 @@ template <typename T, int OPS, bool PER, typename Sink>
 __device__ __forceinline__ void track_point(const TreeView &tv, int64_t k, const uint64_t *__restrict__ kv, int rs,
                                             const T *__restrict__ pos, const T *__restrict__ field,
                                             const T *__restrict__ force, int32_t *__restrict__ ids,
-                                            T *__restrict__ vel, Sink &sink, T *__restrict__ grad = nullptr)
+                                            T *__restrict__ vel, Sink &sink, T *__restrict__ grad = nullptr,
+                                            const int32_t *__restrict__ hid = nullptr)
 {
     const uint64_t word = kv ? kv[k] : 0ull;
     const int64_t kp = (int64_t)rs * k;
     const T X[3] = {pos[kp], pos[kp + 1], pos[kp + 2]};
-    track_point_at<T, OPS, PER, Sink>(tv, k, kv != nullptr, word, X, rs, field, force, ids, vel, sink, grad);
+    track_point_at<T, OPS, PER, Sink>(tv, k, kv != nullptr, word, X, rs, field, force, ids, vel, sink, grad, hid);
 }
 
 // Process points [start, end) of one tile with all threads of the workgroup.
@@ -502,11 +526,11 @@ __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, i
                                             const uint64_t *__restrict__ kv, int rs, const T *__restrict__ pos,
                                             const T *__restrict__ field, const T *__restrict__ force,
                                             int32_t *__restrict__ ids, T *__restrict__ vel, Sink &sink,
-                                            T *__restrict__ grad = nullptr)
+                                            T *__restrict__ grad = nullptr, const int32_t *__restrict__ hid = nullptr)
 {
     if (!kv) {
         for (int64_t k = start + threadIdx.x; k < end; k += blockDim.x)
-            track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink, grad);
+            track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink, grad, hid);
         return;
     }
     // sorted records: the next point's word and position are loaded before
@@ -526,7 +550,7 @@ __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, i
             Xn[1] = pos[(int64_t)rs * kn + 1];
             Xn[2] = pos[(int64_t)rs * kn + 2];
         }
-        track_point_at<T, OPS, PER, Sink>(tv, k, true, w, X, rs, field, force, ids, vel, sink, grad);
+        track_point_at<T, OPS, PER, Sink>(tv, k, true, w, X, rs, field, force, ids, vel, sink, grad, nullptr);
         if (!more) break;
         k = kn;
         w = wn;
@@ -547,5 +571,14 @@ struct SinkSlots { static constexpr int value = 2048; };
 // tiles of 128 bubble markers already reach more leaves than 512 slots).
 constexpr int64_t kSmallTile = 64;
 constexpr int kSmallSlots = 512;
+
+// Host side of spreading (track.hip): clear the target (ATOMIC overwrite) or
+// the workspace's accumulators, take the fixed-point scale (max |F| over
+// `force` unless the caller already maxed it into ws.fx), and convert the
+// accumulators into field_out.
+int spread_begin(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
+int spread_scale(const ot_tree *t, const FxWs &ws, int dtype, int mode, const void *force, int64_t n, hipStream_t s);
+int spread_epilogue(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
+FxWs fx_ws(void *work);
 
 }  // namespace ot

@@ -479,9 +479,9 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
         entries += (int64_t)hcnt[t - 1] << (3 * (tv.lev[t] - tv.lev[t - 1]));
     }
     if (entries >= (int64_t(1) << 40)) return fail(OT_ERR_CAPACITY, "ot_build_tree: descent table too large");
-    DevBuf table, flags, ids, stmp, fx;
+    DevBuf table, flags, ids, stmp;
     if ((rc = dalloc(table, entries * 4)) || (rc = dalloc(flags, n * 4)) || (rc = dalloc(ids, n * 4)) ||
-        (rc = dalloc(stmp, scan_tmp_words(n) * 4)) || (rc = dalloc(fx, (size_t)n * 3 * 8)))
+        (rc = dalloc(stmp, scan_tmp_words(n) * 4)))
         return rc;
     hipLaunchKernelGGL(k_fill_u32, dim3(2048), dim3(256), 0, s, (uint32_t *)table.p, entries, 0xFFFFFFFFu);
     for (int t = 0; t < tv.nlev; ++t) {
@@ -517,9 +517,9 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
     tr->table = (uint32_t *)table.release();
     tr->table_entries = entries;
     tv.table = tr->table;
+    tv.levels = tr->levels;
+    tv.nleaf = (int32_t)n;
     tr->view = tv;
-    tr->fx_acc = (unsigned long long *)fx.release();
-    tr->scratch = (unsigned *)scratch.release();
     *out = tr;
     return OT_OK;
 }
@@ -534,8 +534,6 @@ extern "C" int ot_destroy_tree(ot_tree *t)
     (void)hipFree(t->keys);
     (void)hipFree(t->levels);
     (void)hipFree(t->table);
-    (void)hipFree(t->fx_acc);
-    (void)hipFree(t->scratch);
     (void)hipSetDevice(cur);
     delete t;
     return OT_OK;
@@ -550,7 +548,7 @@ extern "C" int ot_tree_info_get(const ot_tree *t, ot_tree_info *info)
     info->periodic = t->periodic;
     info->table_levels = t->view.nlev;
     info->table_bytes = t->table_entries * 4;
-    info->workspace_bytes = t->n_leaves * 3 * 8;
+    info->workspace_bytes = spread_ws_bytes(t->n_leaves);
     return OT_OK;
 }
 

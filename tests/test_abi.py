@@ -26,6 +26,7 @@ def ot():
 def test_header_declares_the_boundary():
     names = _declared()
     for n in ("ot_build_tree", "ot_locate", "ot_interpolate", "ot_spread", "ot_track", "ot_grad_pos",
+              "ot_interp_grad_pos", "ot_spread_grad_pos", "ot_spread_workspace_bytes",
               "ot_batch_plan_create", "ot_batch_run", "ot_destroy_tree", "ot_strerror", "ot_last_error"):
         assert n in names
 
@@ -92,15 +93,28 @@ def test_backward_host_side_validation(ot):
     L = ot.lib
     dummy = ctypes.c_void_p(0x1000)
     # both outputs NULL: nothing to compute
-    assert L.ot_interp_backward(dummy, dummy, dummy, dummy, 0, 10, 1, 0, None, None, None) == -1
+    assert L.ot_interp_backward(dummy, dummy, dummy, dummy, None, 0, 10, 1, 0, None, None, None, None) == -1
     assert b"both outputs are NULL" in L.ot_last_error()
-    assert L.ot_spread_backward(dummy, dummy, dummy, dummy, 0, 10, None, None, None) == -1
+    assert L.ot_spread_backward(dummy, dummy, dummy, dummy, None, 0, 10, None, None, None) == -1
     # no tree
-    assert L.ot_interp_backward(None, dummy, dummy, dummy, 0, 10, 1, 0, dummy, dummy, None) == -1
+    assert L.ot_interp_backward(None, dummy, dummy, dummy, None, 0, 10, 1, 0, dummy, dummy, None, None) == -1
     assert b"tree is NULL" in L.ot_last_error()
-    assert L.ot_spread_backward(None, dummy, dummy, dummy, 0, 10, dummy, None, None) == -1
+    assert L.ot_spread_backward(None, dummy, dummy, dummy, None, 0, 10, dummy, None, None) == -1
     # no points: nothing per point to compute, whatever the outputs
-    assert L.ot_spread_backward(dummy, dummy, dummy, None, 0, 0, None, None, None) == 0
+    assert L.ot_spread_backward(dummy, dummy, dummy, None, None, 0, 0, None, None, None) == 0
+
+
+def test_ids_and_workspace_host_side_validation(ot):
+    """The calls that take caller host ids and a spreading workspace check
+    their arguments before any device work."""
+    L = ot.lib
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.ot_spread_workspace_bytes(None) == 0
+    assert L.ot_interpolate(None, dummy, dummy, dummy, 0, 10, dummy, None) == -1
+    assert L.ot_spread(None, dummy, dummy, dummy, 0, 10, 1, 0, dummy, None, None) == -1
+    for fn in (L.ot_grad_pos, L.ot_interp_grad_pos, L.ot_spread_grad_pos):
+        assert fn(None, dummy, dummy, dummy, dummy, 0, 10, dummy, None) == -1
+        assert b"tree is NULL" in L.ot_last_error()
 
 
 def test_batch_gradient_ops_host_side_validation(ot):
