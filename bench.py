@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-sort", action="store_true", help="process points in input order (no in-step sort)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (use --block/--tile/--grid)")
+    ap.add_argument("--host-major", action="store_true",
+                    help="sorted plans use the host-major pass instead of the per-point pass")
     ap.add_argument("--presort-shift", type=int, default=0,
                     help="with --presorted: order by host id >> shift (6 mimics the in-step binning)")
     ap.add_argument("--presorted", action="store_true",
@@ -180,7 +182,8 @@ def main():
     fout = torch.empty((tree.n_leaves, 3), dtype=dt, device=dev)
     offsets = [int(v) for v in w.instances]
     ops = [ot.OT_OP_LOCATE | ot.OT_OP_INTERPOLATE | ot.OT_OP_SPREAD] * (len(offsets) - 1)
-    shape = {"block": args.block, "tile": args.tile, "grid": args.grid, "sort_points": not args.no_sort}
+    shape = {"block": args.block, "tile": args.tile, "grid": args.grid, "sort_points": not args.no_sort,
+             "host_major": args.host_major}
     tune_ms = None
     if not args.no_tune:
         from paper_2605_20565_amd import tune as tuner
@@ -189,7 +192,8 @@ def main():
         best, timings = tuner.tune(tree, offsets, ops, pos, field, force, dt, args.mode, candidates=cands, reps=3,
                                    cache_path=None, log=log)
         tune_ms = timings
-        shape = {"block": best.block, "tile": best.tile, "grid": best.grid, "sort_points": best.sort_points}
+        shape = {"block": best.block, "tile": best.tile, "grid": best.grid, "sort_points": best.sort_points,
+                 "host_major": args.host_major}
         log(f"[bench] tuned in {time.perf_counter() - t_t:.1f}s: {best.label()}")
     plan = ot.BatchPlan(tree, offsets, ops, dtype=dt, mode=args.mode, **shape)
     n_tiles, grid = plan.shape()
@@ -221,6 +225,7 @@ def main():
         kms.append(plan.last_kernel_ms())
     plan.set_timing(False)
     kernel_ms = float(np.mean(kms))
+    hm_windows, hm_handed = plan.windows()
 
     # touched leaves: leaves that receive a weight from at least one point
     ones = torch.ones_like(pos)
@@ -255,7 +260,8 @@ def main():
                    "path": "batched persistent kernel, HIP graph" + (", in-step sort of points by host leaf"
                                                                       if shape["sort_points"] else ""),
                    "block": shape["block"] or "library default", "tile": shape["tile"] or "library default",
-                   "tiles": n_tiles, "workgroups": grid, "autotuned": not args.no_tune},
+                   "tiles": n_tiles, "workgroups": grid, "autotuned": not args.no_tune,
+                   "host_major_windows": hm_windows, "windows_to_per_point_pass": hm_handed},
         "roofline": roofline,
     }
     if not args.no_cpu:

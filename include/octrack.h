@@ -140,15 +140,15 @@ typedef struct {
  * workgroup's spreading table.  Needs the same ops for every instance. */
 #define OT_TUNE_SORT_POINTS 1
 
-/* Sorted plans whose instances interpolate or spread (without gradient ops)
- * run a host-major pass: each window of 256 sorted points is ranked by host
- * in LDS, every distinct host's 27 node leaves and field values are taken
- * once and shared by its points, and the points' spreading sums for one
- * host are added up in registers before one LDS add per node and component
- * (the same rounded fixed-point contributions, so FIXED results are equal
- * bit for bit).  Windows whose hosts are too spread out go to the per-point
- * pass.  OT_TUNE_PER_POINT keeps such plans on the per-point pass. */
-#define OT_TUNE_PER_POINT 2
+/* Host-major pass for sorted plans whose instances interpolate or spread
+ * (without gradient ops): each window of 256 sorted points is ranked by
+ * host in LDS, every distinct host's 27 node leaves and field values are
+ * taken once and shared by its points, and the points' spreading sums for
+ * one host are added up in registers before one LDS add per node and
+ * component (the same rounded fixed-point contributions, so FIXED results
+ * are equal bit for bit).  Windows whose hosts are too spread out go to the
+ * per-point pass.  Needs OT_TUNE_SORT_POINTS. */
+#define OT_TUNE_HOST_MAJOR 2
 
 /* Morton keys of leaf anchors (Sec. 3.1: leaves are ordered along the
  * Z-curve).  anchors: (n, 3) uint32, each < 2^l_max.  keys: (n,) uint64.
@@ -403,7 +403,7 @@ int ot_batch_last_kernel_ms(const ot_batch_plan *plan, float *ms);
 /* Tiles and workgroups a plan uses (host ints, either may be NULL). */
 int ot_batch_plan_shape(const ot_batch_plan *plan, int64_t *n_tiles, int32_t *grid);
 
-/* Host-major plans (see OT_TUNE_PER_POINT): the number of 256-point windows
+/* Host-major plans (OT_TUNE_HOST_MAJOR): the number of 256-point windows
  * (0 for other plans) and how many of them the last completed run handed to
  * the per-point pass (host ints, either may be NULL).  Synchronises with the
  * device to read the count. */

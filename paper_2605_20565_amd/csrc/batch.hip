@@ -154,9 +154,9 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
             return fail(OT_ERR_OOM, "ot_batch_plan_create: sort buffers");
         }
     }
-    // sorted forward plans that interpolate or spread take the host-major pass
+    // sorted forward plans that interpolate or spread may take the host-major pass
     p->use_hm = sort_points && !p->grad_plan && (ops_all & (kOpInterp | kOpSpread)) != 0 &&
-                !(tuning && (tuning->flags & OT_TUNE_PER_POINT)) && p->n_points > 0;
+                tuning && (tuning->flags & OT_TUNE_HOST_MAJOR) && p->n_points > 0;
     if (p->use_hm) {
         p->n_win = (p->n_points + kHmWindow - 1) / kHmWindow;
         if (hipMalloc((void **)&p->fb_list, (size_t)p->n_win * 4) != hipSuccess) {

@@ -34,7 +34,7 @@ struct ot_batch_plan {
     void *srec[2];            // position (+ force) records in sorted order
     void *sws;                // counting workspace
     void *fxws;               // fixed-point spreading workspace (FIXED plans that spread)
-    // host-major pass (sorted forward plans unless OT_TUNE_PER_POINT)
+    // host-major pass (sorted forward plans with OT_TUNE_HOST_MAJOR)
     bool use_hm;
     int hm_grid;
     int64_t n_win;            // windows of kHmThreads sorted points

@@ -74,10 +74,10 @@ def test_host_major_equals_per_point_and_plain(ot, request, dtype, tree):
     pts = as_dtype(_points(spec, rng, 200_000, 3000), dtype)
     frc = as_dtype(rng.standard_normal(pts.shape), dtype)
     fld = as_dtype(rng.standard_normal((spec.n_leaves, 3)), dtype)
-    ids, vel, fo, (nw, fb) = _run(ot, t, pts, frc, fld, dtype, "fixed", sort_points=True)
+    ids, vel, fo, (nw, fb) = _run(ot, t, pts, frc, fld, dtype, "fixed", sort_points=True, host_major=True)
     assert nw == (pts.shape[0] + 255) // 256
     assert 0 < fb < nw // 2, (nw, fb)   # most windows host-major, the marker windows handed over
-    ids_p, vel_p, fo_p, (nw_p, _) = _run(ot, t, pts, frc, fld, dtype, "fixed", sort_points=True, per_point=True)
+    ids_p, vel_p, fo_p, (nw_p, _) = _run(ot, t, pts, frc, fld, dtype, "fixed", sort_points=True)
     assert nw_p == 0
     assert torch.equal(ids, ids_p) and torch.equal(vel, vel_p) and torch.equal(fo, fo_p)
     P, F, U = to_dev(pts, dtype), to_dev(frc, dtype), to_dev(fld, dtype)
@@ -99,7 +99,7 @@ def test_host_major_atomic_within_bound(ot, band, dtype):
     pts = as_dtype(_points(spec, rng, 100_000, 2000), dtype)
     frc = as_dtype(rng.standard_normal(pts.shape), dtype)
     fld = as_dtype(rng.standard_normal((spec.n_leaves, 3)), dtype)
-    ids, vel, fo, (nw, fb) = _run(ot, t, pts, frc, fld, dtype, "atomic", sort_points=True)
+    ids, vel, fo, (nw, fb) = _run(ot, t, pts, frc, fld, dtype, "atomic", sort_points=True, host_major=True)
     assert fb < nw
     P, U = to_dev(pts, dtype), to_dev(fld, dtype)
     assert torch.equal(vel, t.interpolate(U, P))
@@ -116,7 +116,7 @@ def test_host_major_op_subsets(ot, band, ops):
     pts = as_dtype(_points(spec, rng, 60_000, 500), dtype)
     frc = as_dtype(rng.standard_normal(pts.shape), dtype)
     fld = as_dtype(rng.standard_normal((spec.n_leaves, 3)), dtype)
-    ids, vel, fo, _ = _run(ot, t, pts, frc, fld, dtype, "fixed", ops=ops, sort_points=True)
+    ids, vel, fo, _ = _run(ot, t, pts, frc, fld, dtype, "fixed", ops=ops, sort_points=True, host_major=True)
     P, F, U = to_dev(pts, dtype), to_dev(frc, dtype), to_dev(fld, dtype)
     if ops & 1:
         assert torch.equal(ids, t.locate(P))
@@ -143,7 +143,7 @@ def test_host_major_dense_hosts_and_full_windows(ot, band):
     pts = as_dtype(np.concatenate([one, two, one[:300] * 0.5 + 0.3]), dtype)
     frc = as_dtype(rng.standard_normal(pts.shape), dtype)
     fld = as_dtype(rng.standard_normal((spec.n_leaves, 3)), dtype)
-    ids, vel, fo, _ = _run(ot, t, pts, frc, fld, dtype, "fixed", sort_points=True)
+    ids, vel, fo, _ = _run(ot, t, pts, frc, fld, dtype, "fixed", sort_points=True, host_major=True)
     P, F, U = to_dev(pts, dtype), to_dev(frc, dtype), to_dev(fld, dtype)
     assert torch.equal(ids, t.locate(P))
     assert torch.equal(vel, t.interpolate(U, P))
