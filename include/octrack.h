@@ -208,6 +208,24 @@ int64_t ot_spread_workspace_bytes(const ot_tree *tree);
 int ot_spread(const ot_tree *tree, const void *force, const void *pos, const int32_t *ids, int32_t dtype,
               int64_t n, int32_t mode, int32_t accumulate, void *field_out, void *work, void *stream);
 
+/* Fixed-point spreading for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): ot_spread with its workspace taken from a static device array
+ * of 256 + 24 * OT_NOALLOC_MAX_LEAVES bytes (about 24 MiB) that the library
+ * holds on every device it runs on until the process ends.  The call
+ * allocates nothing; the caller still passes inputs and outputs.  Every call
+ * on one device shares that device's array: calls that overlap on one
+ * device (several streams or threads) race and give wrong results.  The
+ * array keeps the last call's contents; each call clears what it needs.
+ * FIXED mode only uses the array (ATOMIC mode runs ot_spread, which
+ * allocates nothing in that mode).  Errors: as ot_spread, and
+ * OT_ERR_CAPACITY for a tree with more than OT_NOALLOC_MAX_LEAVES leaves in
+ * FIXED mode, OT_ERR_INVALID when the current device is not the tree's. */
+#define OT_NOALLOC_MAX_LEAVES 1048576
+int ot_spread_noalloc(const ot_tree *tree, const void *force, const void *pos, const int32_t *ids,
+                      int32_t dtype, int64_t n, int32_t mode, int32_t accumulate, void *field_out,
+                      void *stream);
+
 /* One fused pass over the points: host search, interpolation of `field`
  * and spreading of `force` share the stencil.  ops: OT_OP_* bits; ids
  * (output of the search), vel, force/field_out may be NULL when their op is

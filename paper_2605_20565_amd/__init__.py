@@ -66,7 +66,7 @@ EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_g
            "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums",
            "ot_relocate", "ot_leaf_splitters", "ot_find_owner", "ot_particle_step", "ot_interp_backward",
            "ot_spread_backward", "ot_batch_run_grad", "ot_interp_grad_pos", "ot_spread_grad_pos",
-           "ot_spread_workspace_bytes", "ot_batch_plan_windows")
+           "ot_spread_workspace_bytes", "ot_batch_plan_windows", "ot_spread_noalloc")
 
 
 def _load():
@@ -84,6 +84,7 @@ def _load():
         "ot_locate": [P, P, i32, i64, P, P],
         "ot_interpolate": [P, P, P, P, i32, i64, P, P],
         "ot_spread": [P, P, P, P, i32, i64, i32, i32, P, P, P],
+        "ot_spread_noalloc": [P, P, P, P, i32, i64, i32, i32, P, P],
         "ot_track": [P, i32, P, P, P, i32, i64, i32, i32, P, P, P, P, P],
         "ot_grad_pos": [P, P, P, P, P, i32, i64, P, P],
         "ot_interp_grad_pos": [P, P, P, P, P, i32, i64, P, P],
