@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=3_000_000, help="points in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip side measurements")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the side measurements on workloads 3 and 4 (about two minutes of generation)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 1 GiB device copy (reference kernel for rocprofv3 byte counters)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -239,11 +241,14 @@ def main():
         if tr.get("kernel_hash") == kernel_source_hash() and tr.get("dtype") == args.dtype \
                 and tr.get("mode") == args.mode and tr.get("config") == args.config:
             traffic = tr.get("bytes_per_launch")
+    step_gbps = alg_bytes / (ms_per_step * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "k_batch", "kernel_ms": round(kernel_ms, 4), "algorithmic_bytes": int(alg_bytes),
-                "touched_leaves": touched}
-    log(f"[bench] k_batch {kernel_ms:.3f} ms, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBPS:.1%} of peak)")
+                "kernel": "k_hm + k_batch" if args.host_major else "k_batch", "kernel_ms": round(kernel_ms, 4),
+                "algorithmic_bytes": int(alg_bytes), "touched_leaves": touched,
+                "step_achieved": round(step_gbps, 1), "step_frac": round(step_gbps / HBM_PEAK_GBPS, 4)}
+    log(f"[bench] k_batch {kernel_ms:.3f} ms, {achieved:.0f} GB/s algorithmic ({achieved / HBM_PEAK_GBPS:.1%} of peak); "
+        f"whole step {step_gbps:.0f} GB/s ({step_gbps / HBM_PEAK_GBPS:.1%})")
 
     extra = {}
     if not args.no_extra:
@@ -315,6 +320,7 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
                    max(3, args.steps // 2))
     pl64.close()
     res["fp64_batched"] = {"ms_per_step": round(ms64b, 4), "value": n / (ms64b * 1e-3), "spread_mode": "fixed"}
+    res["speedup_vs_fp64_batched"] = round(ms64b / ms_main, 3)
     del p64, f64, fl64, i64, v64, o64
 
     # one plain fused launch per instance (the alternative to one batched pass)
@@ -372,6 +378,8 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
 
     # launch latency on the small workload 1 (11k points; latency bound, so no roofline figure)
     res["config1_latency_us"] = config1_latency(dev, dt, args.mode, ot, torch, timeit)
+    # workload 1 as its configuration states it: the plain method in FP64
+    res["config1_fp64_latency_us"] = config1_latency(dev, torch.float64, args.mode, ot, torch, timeit)
 
     # copy bandwidth for context
     a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -382,6 +390,152 @@ def side_measurements(args, w, tree, pos, force, field, plan, step, dev, dt, ot,
 
     # error against the oracle on a sample of the same inputs
     res["error_vs_oracle"] = oracle_check(w, tree, dev, dt, torch)
+    if not args.no_workloads and args.config == 2:
+        del ids_p, vel_p, fo_p
+        torch.cuda.empty_cache()
+        res["workload3"] = workload3_measure(args, dev, ot, torch, timeit)
+        torch.cuda.empty_cache()
+        res["workload4"] = workload4_measure(args, dev, ot, torch, timeit)
+        torch.cuda.empty_cache()
+    return res
+
+
+def _touched(tree, P):
+    ones = P.new_ones(P.shape)
+    return int((tree.spread(ones, P, mode="atomic").abs().sum(dim=1) > 0).sum().item())
+
+
+def _roof(n, touched, ms, dtype):
+    gbps = (n * BYTES_PER_POINT[dtype] + touched * BYTES_PER_LEAF[dtype]) / (ms * 1e-3) / 1e9
+    return {"algorithmic_GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+
+
+def _workload_on_gpu(w, dev, dt, ot, torch):
+    tree = ot.Tree.from_anchors(torch.from_numpy(w.tree.anchors.astype(np.int32)).to(dev),
+                                torch.from_numpy(w.tree.levels).to(dev), w.tree.l_min, w.tree.l_max, w.tree.periodic)
+    P = torch.from_numpy(w.points).to(dev, dt)
+    F = torch.from_numpy(w.forces).to(dev, dt)
+    U = tree.permute_rows(torch.from_numpy(w.field).to(dev, dt))
+    return tree, P, F, U
+
+
+def workload3_measure(args, dev, ot, torch, timeit):
+    """Workload 3 (256 bubbles of log-uniform size + 64 particle groups, 320
+    uneven instances): one batched, sorted, graph-replayed pass against one
+    plain fused launch per instance, FP32 FIXED."""
+    import synth
+    t0 = time.time()
+    w = synth.workload(3)
+    log(f"[bench] workload cfg3: {w.tree.n_leaves} leaves, {w.n_points} points ({time.time() - t0:.1f}s)")
+    tree, P, F, U = _workload_on_gpu(w, dev, torch.float32, ot, torch)
+    n = P.shape[0]
+    offs = [int(v) for v in w.instances]
+    ids = torch.empty(n, dtype=torch.int32, device=dev)
+    vel = torch.empty_like(P)
+    fo = torch.empty_like(U)
+    plan = ot.BatchPlan(tree, offs, [7] * (len(offs) - 1), dtype=torch.float32, mode="fixed", sort_points=True,
+                        host_major=args.host_major)
+    ms_b = timeit(lambda: plan.run(P, field=U, force=F, ids=ids, vel=vel, field_out=fo), 10)
+    plan.close()
+
+    def per_instance():
+        for i in range(len(offs) - 1):
+            a, b = offs[i], offs[i + 1]
+            tree.track(P[a:b], field=U, force=F[a:b], mode="fixed", ids=ids[a:b], vel=vel[a:b], field_out=fo,
+                       accumulate=i > 0)
+    ms_i = timeit(per_instance, 2)
+    touched = _touched(tree, P)
+    out = {"leaves": int(tree.n_leaves), "points": int(n), "instances": len(offs) - 1,
+           "batched_ms_per_step": round(ms_b, 4), "batched_points_per_s": n / (ms_b * 1e-3),
+           "per_instance_launches_ms_per_step": round(ms_i, 4), "batched_speedup": round(ms_i / ms_b, 2),
+           "touched_leaves": touched, "batched_roofline": _roof(n, touched, ms_b, "f32"),
+           "path": "batched persistent kernel, HIP graph, in-step sort; FP32, FIXED"}
+    tree.close()
+    return out
+
+
+def workload4_measure(args, dev, ot, torch, timeit):
+    """Workload 4 (10^8 particles in Gaussian shells, sigma = 2 finest dx,
+    ~26 per finest leaf in the bands): FIXED vs FP32-atomic vs FP64 batched
+    spreading steps, FIXED's bitwise reproducibility over 5 runs, and the
+    error against the oracle on a 10^7-point subsample of the same points."""
+    import synth
+    t0 = time.time()
+    w = synth.workload(4)
+    log(f"[bench] workload cfg4: {w.tree.n_leaves} leaves, {w.n_points} points ({time.time() - t0:.1f}s)")
+    tree, P, F, U = _workload_on_gpu(w, dev, torch.float32, ot, torch)
+    n = P.shape[0]
+    offs = [int(v) for v in w.instances]
+    ops = [7] * (len(offs) - 1)
+    ids = torch.empty(n, dtype=torch.int32, device=dev)
+    vel = torch.empty_like(P)
+    fo = torch.empty_like(U)
+    touched = _touched(tree, P)
+    res = {"leaves": int(tree.n_leaves), "points": int(n), "touched_leaves": touched}
+    for mode in ("fixed", "atomic"):
+        pl = ot.BatchPlan(tree, offs, ops, dtype=torch.float32, mode=mode, sort_points=True,
+                          host_major=args.host_major)
+        ms = timeit(lambda: pl.run(P, field=U, force=F, ids=ids, vel=vel, field_out=fo), 5)
+        res[f"f32_{mode}"] = {"ms_per_step": round(ms, 3), "points_per_s": n / (ms * 1e-3),
+                              **_roof(n, touched, ms, "f32")}
+        if mode == "fixed":
+            outs = []
+            for _ in range(5):
+                pl.run(P, field=U, force=F, ids=ids, vel=vel, field_out=fo)
+                torch.cuda.synchronize()
+                outs.append(fo.view(torch.int32).clone())
+            res["fixed_bitwise_repro_5_runs"] = all(torch.equal(outs[0], o) for o in outs[1:])
+            del outs
+        pl.close()
+    # FP64 batched (FIXED)
+    P64, F64 = P.double(), F.double()
+    U64 = tree.permute_rows(torch.from_numpy(w.field).to(dev, torch.float64))
+    vel64, fo64 = torch.empty_like(P64), torch.empty_like(U64)
+    pl = ot.BatchPlan(tree, offs, ops, dtype=torch.float64, mode="fixed", sort_points=True,
+                      host_major=args.host_major)
+    ms = timeit(lambda: pl.run(P64, field=U64, force=F64, ids=ids, vel=vel64, field_out=fo64), 3)
+    pl.close()
+    res["f64_fixed"] = {"ms_per_step": round(ms, 3), "points_per_s": n / (ms * 1e-3), **_roof(n, touched, ms, "f64")}
+    del P64, F64, U64, vel64, fo64, vel, fo
+    torch.cuda.empty_cache()
+    # the oracle on a 10^7-point subsample (FP32-rounded inputs, the same batched path on the subsample)
+    import oracle
+    rng = np.random.default_rng(404)
+    m = min(10_000_000, n)
+    sel = np.sort(rng.choice(n, size=m, replace=False))
+    pts = w.points[sel].astype(np.float32).astype(np.float64)
+    frc = w.forces[sel].astype(np.float32).astype(np.float64)
+    o = oracle.Tree.from_anchors(w.tree.anchors, w.tree.levels, w.tree.l_min, w.tree.l_max, w.tree.periodic)
+    fld = o.permute_rows(w.field).astype(np.float32).astype(np.float64)
+    Ps, Fs = torch.from_numpy(pts).to(dev, torch.float32), torch.from_numpy(frc).to(dev, torch.float32)
+    Us = torch.from_numpy(fld).to(dev, torch.float32)
+    pl = ot.BatchPlan(tree, [0, m], [7], dtype=torch.float32, mode="fixed", sort_points=True,
+                      host_major=args.host_major)
+    ids_s = torch.empty(m, dtype=torch.int32, device=dev)
+    vel_s, fo_s = torch.empty_like(Ps), torch.empty_like(Us)
+    pl.run(Ps, field=Us, force=Fs, ids=ids_s, vel=vel_s, field_out=fo_s)
+    torch.cuda.synchronize()
+    pl.close()
+    t1 = time.time()
+    want_ids = o.locate(pts)
+    Uo, S = o.interpolate(fld, pts, with_scale=True)
+    fo_o, Sf, cnt, A = o.spread(frc, pts, with_scale=True)
+    log(f"[bench] oracle on the cfg4 subsample: {time.time() - t1:.1f}s")
+    mm = float(np.abs(frc).max())
+    _, E = math.frexp(m * mm)
+    _, Ef = math.frexp(mm)
+    q = math.ldexp(1.0, -min(62 - E, 51 - Ef))
+    eu = np.abs(vel_s.cpu().double().numpy() - Uo) / np.maximum(S, 1e-300)
+    bound = 1e-5 * Sf + 2.0 ** -110 * A + cnt[:, None] * 0.5 * q
+    got = fo_s.cpu().double().numpy()
+    touched_s = Sf > 0
+    ef = np.abs(got - fo_o) / np.maximum(bound, 1e-300)
+    res["error_vs_oracle_1e7_subsample"] = {
+        "sample": m, "ids_mismatch": int((ids_s.cpu().numpy() != want_ids).sum()),
+        "interp_scaled_max": float(eu.max()), "interp_tol": 1e-5,
+        "spread_err_over_bound_max": float(ef[touched_s].max()),
+        "spread_scaled_p99": float(np.percentile((np.abs(got - fo_o) / np.maximum(Sf, 1e-300))[touched_s], 99))}
+    tree.close()
     return res
 
 
@@ -484,6 +638,12 @@ def mdf_measure(w, tree, field, dev, dt, mode, torch, timeit, n_iter=5):
     u = field.clone()
     work = torch.empty(max(1, int(tree_mdf_bytes(tree, P))), dtype=torch.uint8, device=dev)
     ms = timeit(lambda: tree.mdf(u, P, tgt, n_iter, mode=mode, inplace=True, work=work), 10)
+    # the same call captured once in a HIP graph and replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        tree.mdf(u, P, tgt, n_iter, mode=mode, inplace=True, work=work)
+    ms_graph = timeit(g.replay, 10)
+    del g
     # the bodies' IBM force and torque from the marker forces (per-body sums)
     import paper_2605_20565_amd as ot
     _, f_lag, _ = tree.mdf(u, P, tgt, n_iter, mode=mode, work=work)
@@ -491,7 +651,8 @@ def mdf_measure(w, tree, field, dev, dt, mode, torch, timeit, n_iter=5):
     cen = torch.tensor([w.spheres[i].centre for i in range(len(idx))], dtype=dt, device=dev)
     us = timeit(lambda: ot.body_sums(f_lag, P, offs, cen, 1.0), 20) * 1e3
     return {"markers": int(P.shape[0]), "iterations": n_iter, "ms_per_step": round(ms, 4),
-            "ms_per_iteration": round(ms / n_iter, 4), "spread_mode": mode,
+            "ms_per_iteration": round(ms / n_iter, 4), "graph_replay_ms_per_step": round(ms_graph, 4),
+            "spread_mode": mode,
             "body_force_torque_us": round(us, 1), "bodies": len(idx)}
 
 
@@ -536,14 +697,14 @@ def oracle_check(w, tree, dev, dt, torch, n_sample=20000):
     U, S = o.interpolate(fld, pts, with_scale=True)
     f, Sf, cnt, A = o.spread(frc, pts, with_scale=True)
     eu = np.abs(vel.cpu().numpy() - U) / np.maximum(S, 1e-300)
-    # spreading: per leaf against tol * sum|w F| + 2^-46 sum|F| (the FP64 weights'
-    # absolute precision) + half a fixed-point quantum per contribution
+    # spreading: per leaf against tol * sum|w F| + 2^-110 sum|F| (the oracle's
+    # binary128 weights' absolute precision) + half a fixed-point quantum per contribution
     m = float(np.abs(frc).max())
     _, E = math.frexp(len(frc) * m)
     _, Ef = math.frexp(m)
     q = math.ldexp(1.0, -min(62 - E, 51 - Ef))
     tol = 1e-5 if dt == torch.float32 else 1e-12
-    bound = tol * Sf + 2.0 ** -46 * A + cnt[:, None] * 0.5 * q
+    bound = tol * Sf + 2.0 ** -110 * A + cnt[:, None] * 0.5 * q
     ef = np.abs(fo.cpu().numpy() - f) / np.maximum(bound, 1e-300)
     touched = Sf > 0
     return {"sample": int(len(sel)), "ids_mismatch": int((ids.cpu().numpy() != o.locate(pts)).sum()),
@@ -553,8 +714,8 @@ def oracle_check(w, tree, dev, dt, torch, n_sample=20000):
 
 
 def cpu_baseline(w, n_sample):
-    """The FP64 oracle (plain C, OpenMP over points for search and
-    interpolation, serial spreading) on a bounded sample of the workload."""
+    """The FP64 oracle (plain C, OpenMP over points; spreading into per-thread
+    fields merged in thread order) on a bounded sample of the workload."""
     import oracle
     o = oracle.Tree.from_anchors(w.tree.anchors, w.tree.levels, w.tree.l_min, w.tree.l_max, w.tree.periodic)
     fld = o.permute_rows(w.field)

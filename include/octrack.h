@@ -320,6 +320,24 @@ int ot_body_sums(const void *vec, const void *pos, int64_t n, const int64_t *off
                  const void *centres, const void *dv, double dv_all, int32_t dtype, int32_t periodic,
                  double *sum_out, double *moment_out, void *stream);
 
+/* Mean IBM-force subtraction (Sec. 5.2: in a fully periodic box the
+ * domain average of the IBM forcing is removed at every step, so that the
+ * dispersed phase exerts no net force on the fluid).  The leaf field is
+ * constant over each leaf's cube, so its average over the unit cube is
+ *   mean[c] = sum_j field[j][c] 2^(-3 l_j)
+ * (summed in FP64 with a fixed grid and a fixed order: the same bits on
+ * every run), and with subtract != 0 every leaf then gets
+ * field[j][c] - mean[c] (formed in FP64, rounded once to dtype).  field:
+ * (n_leaves, 3) dtype, in place; mean_out: device FP64 (3,), required.
+ * work: 8-byte aligned device buffer of ot_force_mean_workspace_bytes()
+ * bytes, or NULL (allocated on the stream).  The spreading output of this
+ * library is a force density when the forces were scaled by dV_k / dx_l^3
+ * (no cell-volume factor in the weights).  Errors: OT_ERR_INVALID,
+ * OT_ERR_OOM, OT_ERR_HIP. */
+int64_t ot_force_mean_workspace_bytes(void);
+int ot_force_mean(const ot_tree *tree, void *field, int32_t dtype, int32_t subtract, double *mean_out,
+                  void *work, void *stream);
+
 /* Phase I of the migration of Lagrangian points (Algorithm 2), one device.
  *
  * ot_relocate: ids (n,) holds each point's previous host leaf id (or -1) on

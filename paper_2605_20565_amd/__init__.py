@@ -66,7 +66,8 @@ EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_g
            "ot_batch_plan_destroy", "ot_strerror", "ot_last_error", "ot_mdf", "ot_mdf_workspace_bytes", "ot_body_sums",
            "ot_relocate", "ot_leaf_splitters", "ot_find_owner", "ot_particle_step", "ot_interp_backward",
            "ot_spread_backward", "ot_batch_run_grad", "ot_interp_grad_pos", "ot_spread_grad_pos",
-           "ot_spread_workspace_bytes", "ot_batch_plan_windows", "ot_spread_noalloc")
+           "ot_spread_workspace_bytes", "ot_batch_plan_windows", "ot_spread_noalloc", "ot_force_mean",
+           "ot_force_mean_workspace_bytes")
 
 
 def _load():
@@ -101,6 +102,7 @@ def _load():
         "ot_batch_plan_destroy": [P],
         "ot_mdf": [P, P, P, P, i32, i64, i32, ctypes.c_double, ctypes.c_double, i32, P, P, P, P],
         "ot_body_sums": [P, P, i64, P, i32, P, P, ctypes.c_double, i32, i32, P, P, P],
+        "ot_force_mean": [P, P, i32, i32, P, P, P],
         "ot_relocate": [P, P, i32, i64, P, P, P],
         "ot_leaf_splitters": [P, i32, P, P],
         "ot_find_owner": [P, i32, i32, i32, P, i32, i64, P, P, P],
@@ -114,6 +116,8 @@ def _load():
     L.ot_mdf_workspace_bytes.restype = i64
     L.ot_spread_workspace_bytes.argtypes = [P]
     L.ot_spread_workspace_bytes.restype = i64
+    L.ot_force_mean_workspace_bytes.argtypes = []
+    L.ot_force_mean_workspace_bytes.restype = i64
     L.ot_strerror.argtypes = [i32]
     L.ot_strerror.restype = ctypes.c_char_p
     L.ot_last_error.argtypes = []
@@ -404,6 +408,20 @@ class Tree:
         _check(lib.ot_spread_backward(self._h, _ptr(grad_field), _ptr(force), _ptr(pos), _ptr(ids), _dtype_code(pos),
                                       pos.shape[0], _ptr(gF), _ptr(gx), _stream()))
         return gF, gx
+
+    def force_mean(self, field: torch.Tensor, subtract: bool = True,
+                   work: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Volume average over the unit cube of a leaf field (ot_force_mean), FP64 (3,); with
+        subtract=True the field, in place, loses it (Sec. 5.2's mean IBM-force subtraction)."""
+        if not field.is_contiguous():
+            raise ValueError("field must be contiguous (it is updated in place)")
+        field = _rows3(field, "field")
+        if field.shape[0] != self.n_leaves:
+            raise ValueError("field must be (n_leaves, 3)")
+        mean = torch.empty(3, dtype=torch.float64, device=field.device)
+        _check(lib.ot_force_mean(self._h, _ptr(field), _dtype_code(field), 1 if subtract else 0, _ptr(mean),
+                                 _ptr(work), _stream()))
+        return mean
 
     def relocate(self, pos: torch.Tensor, ids: torch.Tensor, count: bool = True) -> Optional[int]:
         """Update `ids` (previous hosts, int32) in place to the hosts of the

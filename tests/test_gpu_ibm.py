@@ -202,3 +202,34 @@ def test_mdf_walled_tree_markers_outside(ot, dtype):
     u_o, _, _ = _ibm().mdf(o, u0.cpu().double().numpy(), pos.cpu().double().numpy(),
                            target.cpu().double().numpy(), n_iter, dt, rho)
     assert np.abs(ug.cpu().double().numpy() - u_o).max() <= 10 * TOL[dtype] * (1 + np.abs(u_o).max()) * 10
+
+
+@pytest.mark.parametrize("mode", ["fixed", "atomic"])
+def test_mdf_captured_in_one_graph_replays_bitwise(ot, mode):
+    """The whole multi-direct forcing loop (n iterations of interpolate,
+    slip force, spread, correct) captured once in a HIP graph: every replay,
+    with eager work between them, equals the eager call bit for bit."""
+    w = synth.workload(1)
+    t = gpu_tree(w.tree)
+    o = oracle_tree(w.tree)
+    dt_ = torch.float32
+    sph = w.spheres[0]
+    P = to_dev(as_dtype(synth.fibonacci_sphere(sph, 1500), dt_), dt_)
+    rng = np.random.default_rng(31)
+    target = to_dev(as_dtype(0.05 * rng.standard_normal(P.shape), dt_), dt_)
+    u0 = to_dev(as_dtype(o.permute_rows(w.field), dt_), dt_)
+    n_iter, step, rho = 5, 0.5, 1.0
+    nbytes = int(ot.lib.ot_mdf_workspace_bytes(t.handle, P.shape[0], 0))
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    u_e, fl_e, fe_e = t.mdf(u0, P, target, n_iter, step, rho, mode=mode, work=work)
+    torch.cuda.synchronize()
+    u_in = u0.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        u_g, fl_g, fe_g = t.mdf(u_in, P, target, n_iter, step, rho, mode=mode, work=work, inplace=True)
+    for rep in range(3):
+        u_in.copy_(u0)                     # eager work between the replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u_g, u_e) and torch.equal(fl_g, fl_e) and torch.equal(fe_g, fe_e), rep

@@ -370,3 +370,60 @@ def test_autograd_matches_central_differences_fp64(ot):
     # and the linear parts: d/du of <U, gU> is spread(gU); d/dF of <f, gf> is interpolate(gf)
     assert torch.allclose(u.grad, t.spread(gU, X.detach(), mode="atomic"), rtol=0, atol=1e-12)
     assert torch.allclose(F.grad, t.interpolate(gf, X.detach()), rtol=0, atol=1e-12)
+
+
+def test_cfg5_gradient_central_differences_and_oracle(ot):
+    """Workload 5 (10^6 markers on the workload-2 tree): the position
+    gradient of <interpolate(u), gU> + <spread(F), gf> through the pair's
+    autograd backward, against FP64 central differences with h = 1e-4 finest
+    dx (points kept away from cell faces and phi kinks; the gradient holds
+    the host fixed) and against the oracle gradient, in FP64 and FP32.  Each
+    point's terms depend on its own position only, so the differences are
+    taken for a sample with all perturbed positions in one batch, the
+    spreading term through its adjoint <F, interpolate(gf)>."""
+    _say("generating workload 5 (finite differences)")
+    w5 = synth.workload(5)
+    o = oracle_tree(w5.tree)
+    t = gpu_tree(w5.tree)
+    rng = np.random.default_rng(77)
+    k = np.sort(rng.choice(w5.points.shape[0], size=6000, replace=False))
+    pts = w5.points[k]
+    host, level, _ = o.stencil_leaves(pts)
+    s = pts * np.ldexp(1.0, level)[:, None]
+    frac = s - np.floor(s)
+    away = np.all(np.minimum.reduce([np.abs(frac - c) for c in (0.0, 0.5, 1.0)]) > 0.01, axis=1)
+    pts = pts[away][:3000]
+    n = pts.shape[0]
+    fld = o.permute_rows(w5.field)
+    gU = rng.standard_normal((n, 3))
+    F = rng.standard_normal((n, 3))
+    gf = rng.standard_normal((t.n_leaves, 3))
+    for dt in (torch.float64, torch.float32):
+        # the oracle sees exactly the values the GPU sees
+        a_p, a_f, a_u, a_g, a_gf = (as_dtype(v, dt) for v in (pts, F, fld, gU, gf))
+        w1, S1 = o.grad_pos(a_u, a_g, a_p, with_scale=True)
+        w2, S2 = o.grad_pos(a_gf, a_f, a_p, with_scale=True)
+        want = w1 + w2
+        P = to_dev(as_dtype(pts, dt), dt).requires_grad_(True)
+        u = to_dev(as_dtype(fld, dt), dt)
+        Fd = to_dev(as_dtype(F, dt), dt)
+        loss = (ot.interpolate(t, u, P, mode="fixed") * to_dev(as_dtype(gU, dt), dt)).sum() + \
+            (ot.spread(t, Fd, P, mode="fixed") * to_dev(as_dtype(gf, dt), dt)).sum()
+        loss.backward()
+        got = P.grad.double().cpu().numpy()
+        if dt == torch.float64:
+            h = 1e-4 * math.ldexp(1.0, -w5.tree.l_max)
+            X = torch.from_numpy(pts).cuda()
+            uu, gg = torch.from_numpy(fld).cuda(), torch.from_numpy(gf).cuda()
+            GU, FF = torch.from_numpy(gU).cuda(), torch.from_numpy(F).cuda()
+            fd = np.zeros_like(pts)
+            for d in range(3):
+                e = torch.zeros_like(X)
+                e[:, d] = h
+                lp = (t.interpolate(uu, X + e) * GU).sum(1) + (t.interpolate(gg, X + e) * FF).sum(1)
+                lm = (t.interpolate(uu, X - e) * GU).sum(1) + (t.interpolate(gg, X - e) * FF).sum(1)
+                fd[:, d] = ((lp - lm) / (2 * h)).cpu().numpy()
+            scale = np.abs(got).max() + 1.0
+            assert np.abs(got - fd).max() <= 1e-6 * scale
+        # against the oracle gradient on the scaled metric (sum of both terms' scales)
+        assert scaled_err(got, want, S1 + S2) <= TOL[dt]
