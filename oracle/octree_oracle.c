@@ -282,9 +282,10 @@ static inline void nsum(double *s, double *c, double v)
  * indices at level l (o = 0,1,2 for offsets -1,0,+1), whether each node
  * exists, the per-axis 1-D weights ph[d][o] = phi(r) of the distances
  * r = t_d - 1/2 - (o-1) (and phi'(r) in dph when asked), and the leaf
- * holding each of the 27 nodes.  The distance is formed in binary128 from
- * the exact FP64 offset t_d, so it is exact, and phi / phi' are evaluated
- * there and rounded once. */
+ * holding each of the 27 nodes.  The offset t_d = x 2^l - floor(x 2^l) and
+ * the distance are formed in binary128, where both are exact (also for a
+ * point below 0 wrapped by periodicity, whose FP64 offset would round), and
+ * phi / phi' are evaluated there and rounded once. */
 typedef struct {
     int64_t host;
     int level;
@@ -309,10 +310,13 @@ static int build_stencil(const orc_tree *t, const double x[3], stencil *st, int 
     int64_t nidx[3][3];
     for (int d = 0; d < 3; ++d) {
         double s = x[d] * ldexp(1.0, l);     /* position in level-l cell units */
-        double frac = s - floor(s);          /* offset inside the host cell   */
+        /* offset inside the host cell, in binary128 so that it is exact
+         * also for s < 0 (a periodic wrap), where s - floor(s) in FP64 would
+         * round away the distance to the far edge of the support           */
+        __float128 frac = (__float128)s - (__float128)floor(s);
         int64_t i0 = I[d] >> sh;             /* host cell index at level l    */
         for (int o = 0; o < 3; ++o) {
-            __float128 r = (__float128)frac - 0.5Q - (__float128)(o - 1);
+            __float128 r = frac - 0.5Q - (__float128)(o - 1);
             st->ph[d][o] = (double)phi_q(r);
             st->dph[d][o] = want_grad ? (double)dphi_q(r) : 0.0;
             int64_t nd = i0 + (o - 1);

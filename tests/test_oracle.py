@@ -330,6 +330,28 @@ def test_uniform_grid_textbook_interpolation(orc):
     assert np.allclose(U, want, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("delta", [1e-9, 1e-14, 3e-16])
+def test_wrapped_point_far_edge_weight(orc, delta):
+    """A point just below 0 on a periodic uniform grid lies in the last cell
+    at offset 1 - delta m, and the node two cells back (column m - 2) sits at
+    distance 3/2 - delta m, near the edge of the support: its weight is
+    phi(3/2 - eps), eps = delta m, to the oracle's phi precision (FP64
+    relative plus about 2^-113 absolute).  An offset rounded to FP64 first
+    (1 - eps is not representable) would miss eps by up to 2^-53 absolute, a
+    relative error of order 2^-53/eps in eps and twice that in the weight."""
+    level = 3
+    m = 1 << level
+    spec = synth.uniform_tree(level, seed=12)
+    tree = _tree(orc, spec)
+    a = spec.anchors
+    fld = np.repeat((a[:, 0] == m - 2).astype(np.float64)[:, None], 3, axis=1)
+    X = np.array([[-delta, 0.5 / m, 0.5 / m]])
+    U = tree.interpolate(tree.permute_rows(fld), X)
+    eps = delta * m   # exact: a power-of-two scaling
+    want = _edge_phi_conjugate(eps)   # times the y and z weight sums, 1 up to rounding
+    assert U[0] == pytest.approx(np.full(3, want), rel=1e-14, abs=2.0 ** -110), (delta, U[0], want)
+
+
 def _cfg1(orc, periodic=True):
     w = synth.workload(1)
     spec = w.tree
