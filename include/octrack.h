@@ -88,7 +88,11 @@ extern "C" {
  * the result does not depend on execution order (bitwise reproducible).
  * s = min(62 - E, 51 - Ef) with 2^E >= n max|F| and 2^Ef >= max|F| (no leaf
  * sum can overflow, no contribution exceeds 2^51); max over finite
- * components.  The absolute error per contribution is at most 2^-(s+1). */
+ * components.  The absolute error per contribution is at most 2^-(s+1).
+ * Non-finite forces: ATOMIC mode carries a NaN or infinite component to the
+ * leaves that point reaches, as FP arithmetic does; the integer sums of
+ * FIXED mode cannot carry it, so there a force with a non-finite component
+ * makes every value of the output field NaN. */
 #define OT_SPREAD_ATOMIC 0
 #define OT_SPREAD_FIXED  1
 

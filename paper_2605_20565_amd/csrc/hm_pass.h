@@ -259,8 +259,9 @@ __global__ __launch_bounds__(kHmThreads) void k_hm(TreeView tv, int64_t n, int64
             const T sc = (T)(1 << l);
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const T s = X[d] * sc;
-                delta3<T>(s - floor(s), wt[d]);
+                T t, r;
+                cell_offsets<T>(X[d] * sc, t, r);
+                delta3<T>(t, r, wt[d]);
 #pragma unroll
                 for (int o = 0; o < 3; ++o) sh.w[slot][3 * d + o] = wt[d][o];
             }

@@ -132,8 +132,24 @@ __device__ __forceinline__ bool point_cell(const TreeView &tv, T x, T y, T z, ui
     return ok;
 }
 
+// Offsets of a point inside its level-l cell along one axis, from the scaled
+// coordinate s = x 2^l: t = s - floor(s) in [0,1] and r = 1 - t, each formed
+// from s itself.  Whichever is at most 1/2 is then exact (Sterbenz's lemma),
+// negative s (a periodic wrap) included, where 1 - (s - floor(s)) would lose
+// the digits of a small r and with them the relative accuracy of the weight
+// r^2/... of the node at the far edge of the support.  For t <= 1/2 the
+// plain 1 - t is kept: it lies in [1/2, 1], and (floor(s) + 1) could round
+// for |s| beyond the significand.
+template <typename T>
+__device__ __forceinline__ void cell_offsets(T s, T &t, T &r)
+{
+    const T f = floor(s);
+    t = s - f;
+    r = t > T(0.5) ? (f + T(1)) - s : T(1) - t;
+}
+
 // 1-D weights of the three stencil nodes i0-1, i0, i0+1 for a point at
-// fractional offset t in [0,1) inside its level-l cell.  With u = t - 1/2
+// fractional offset t in [0,1) inside its level-l cell, r = 1 - t.  With u = t - 1/2
 // the node distances are u+1, u, u-1, and all three branches of phi share
 // q = sqrt(1 - 3u^2) (substitute |r| = 1+u, |u|, 1-u into the phi equation of
 // Sec. 2.2; -2 + 6|r| - 3r^2 = 1 - 3u^2 for |r| = 1 -+ u):
@@ -146,11 +162,10 @@ __device__ __forceinline__ bool point_cell(const TreeView &tv, T x, T y, T z, ui
 // with u -+ q rewritten the same way where it cancels
 // (u - q = -4t(1-t)/(u+q) for u >= 0, u + q = 4t(1-t)/(q-u) for u < 0).
 template <typename T>
-__device__ __forceinline__ void delta3(T t, T w[3])
+__device__ __forceinline__ void delta3(T t, T s, T w[3])
 {
     const T u = t - T(0.5);
     const T q = sqrt(T(1) - T(3) * u * u);
-    const T s = T(1) - t;
     w[0] = T(2) * s * s / (T(2) - T(3) * u + q);
     w[1] = (T(1) + q) * T(1.0 / 3.0);
     w[2] = T(2) * t * t / (T(2) + T(3) * u + q);
@@ -160,22 +175,20 @@ __device__ __forceinline__ void delta3(T t, T w[3])
 // of the correctly rounded sequences; 1 - 3u^2 lies in [1/4, 1] and the two
 // denominators in [1, 9/2], so neither meets a special case.
 template <>
-__device__ __forceinline__ void delta3<float>(float t, float w[3])
+__device__ __forceinline__ void delta3<float>(float t, float s, float w[3])
 {
     const float u = t - 0.5f;
     const float q = __builtin_amdgcn_sqrtf(1.0f - 3.0f * u * u);
-    const float s = 1.0f - t;
     w[0] = 2.0f * s * s * __builtin_amdgcn_rcpf(2.0f - 3.0f * u + q);
     w[1] = (1.0f + q) * (1.0f / 3.0f);
     w[2] = 2.0f * t * t * __builtin_amdgcn_rcpf(2.0f + 3.0f * u + q);
 }
 
 template <typename T>
-__device__ __forceinline__ void delta3_grad(T t, T w[3], T dw[3])
+__device__ __forceinline__ void delta3_grad(T t, T s, T w[3], T dw[3])
 {
     const T u = t - T(0.5);
     const T q = sqrt(T(1) - T(3) * u * u);
-    const T s = T(1) - t;
     w[0] = T(2) * s * s / (T(2) - T(3) * u + q);
     w[1] = (T(1) + q) * T(1.0 / 3.0);
     w[2] = T(2) * t * t / (T(2) + T(3) * u + q);

@@ -46,7 +46,8 @@ inline void point_sort_key_bits(int64_t n_leaves, int &shift, int &bits)
 // host get n_leaves), ids when ids != null, then ceil(bits / 8) stable
 // passes over id bits [shift, shift + bits); bits >= 1.  force != null: records carry forces
 // too, and when maxbits != null the first pass also atomically maxes the
-// bit pattern of max |F| (finite components) into *maxbits.
+// bit pattern of max |F| (finite components) into maxbits[0] and sets
+// maxbits[1] when a component is not finite.
 template <typename T>
 void point_sort(const TreeView &tv, int64_t n, int64_t n_leaves, int shift, int bits, const T *pos, const T *force,
                 int32_t *ids, PointSortBufs<T> &b, unsigned long long *maxbits, hipStream_t s,

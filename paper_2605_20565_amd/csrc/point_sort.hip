@@ -242,6 +242,7 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     T rv[kItems][R];
     uint32_t lo[kItems];
     unsigned long long mx = 0;
+    bool bad = false;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int li = j * kThreads + threadIdx.x;
@@ -262,8 +263,10 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
             }
             if (maxbits) {
 #pragma unroll
-                for (int c = 3; c < R; ++c)
+                for (int c = 3; c < R; ++c) {
                     if (isfinite(rv[j][c])) mx = std::max(mx, abs_bits_of(rv[j][c]));
+                    else bad = true;
+                }
             }
         }
     }
@@ -300,7 +303,10 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         }
         __syncthreads();
     }
-    if (maxbits) block_max_to(mx, sh_max, maxbits);
+    if (maxbits) {
+        if (bad) atomicOr(maxbits + 1, 1ull);   // the non-finite flag next to max |F|
+        block_max_to(mx, sh_max, maxbits);
+    }
 }
 
 template <typename T, int R>

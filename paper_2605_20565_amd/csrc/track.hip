@@ -35,7 +35,8 @@ int spread_begin(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accu
         }
     } else {
         hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1024), dim3(256), 0, s, ws.acc, n3, 0ull);
-        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &ws.fx->maxbits, (int64_t)1, 0ull);
+        // max |F| and the non-finite flag
+        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &ws.fx->maxbits, (int64_t)2, 0ull);
     }
     OT_HIP(hipGetLastError());
     return OT_OK;

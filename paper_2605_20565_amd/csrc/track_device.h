@@ -20,9 +20,9 @@ enum : int { kModeAtomic = OT_SPREAD_ATOMIC, kModeFixed = OT_SPREAD_FIXED };
 // caller's, or a batch plan's).
 struct FxState {
     unsigned long long maxbits;   // bit pattern of max |F| (IEEE order == value order for >= 0)
+    unsigned long long nonfinite; // != 0: some force component is NaN or infinite
     double scale;                 // 2^s
     double inv;                   // 2^-s
-    unsigned long long pad;
 };
 
 // A spreading workspace: header and n_leaves x 3 int64 accumulators.
@@ -77,8 +77,9 @@ __device__ __forceinline__ void make_stencil(const TreeView &tv, const T X[3], c
     st.valid = 0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const T s = X[d] * sc;
-        delta3<T>(s - floor(s), st.w[d]);
+        T t, r;
+        cell_offsets<T>(X[d] * sc, t, r);
+        delta3<T>(t, r, st.w[d]);
         const int32_t c = (int32_t)(I[d] >> sh);
 #pragma unroll
         for (int o = 0; o < 3; ++o) {
@@ -363,9 +364,9 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
                 const T sc = (T)(1 << st.level);
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
-                    const T s = X[d] * sc;
-                    T wtmp[3];
-                    delta3_grad<T>(s - floor(s), wtmp, dw[d]);
+                    T t, r, wtmp[3];
+                    cell_offsets<T>(X[d] * sc, t, r);
+                    delta3_grad<T>(t, r, wtmp, dw[d]);
 #pragma unroll
                     for (int o = 0; o < 3; ++o) dw[d][o] *= sc;
                     v[d] = force[kp + d];
@@ -441,17 +442,21 @@ __device__ __forceinline__ unsigned long long abs_bits(double v)
 }
 
 // max |F| over finite components (bit patterns of non-negative IEEE values
-// order like the values, so an integer max is exact and order independent).
-// One atomic per workgroup: same-address atomics serialise.
+// order like the values, so an integer max is exact and order independent)
+// into out[0], and out[1] != 0 when some component is not finite.  One
+// atomic per workgroup: same-address atomics serialise.
 template <typename T>
 __global__ __launch_bounds__(256) void k_maxabs(const T *__restrict__ f, int64_t m, unsigned long long *__restrict__ out)
 {
     __shared__ unsigned long long wmax[4];
     unsigned long long best = 0;
+    bool bad = false;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
         const T v = f[i];
         if (isfinite(v)) best = std::max(best, abs_bits(v));
+        else bad = true;
     }
+    if (bad) atomicOr(out + 1, 1ull);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) best = std::max(best, (unsigned long long)__shfl_xor(best, o, 64));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = best;
@@ -495,13 +500,16 @@ __global__ void k_fx_prepare(FxState *fx, int64_t n)
     fx->inv = ldexp(1.0, -s);
 }
 
+// Accumulators to field_out.  A non-finite force cannot be carried by the
+// integer sums, so when one was seen every output value becomes NaN.
 template <typename T>
 __global__ void k_fx_finalize(const unsigned long long *__restrict__ acc, T *__restrict__ out, int64_t n3,
                               const FxState *__restrict__ fx, int accumulate)
 {
     const double inv = fx->inv;
+    const bool poison = fx->nonfinite != 0ull;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3; i += (int64_t)gridDim.x * blockDim.x) {
-        const T v = (T)((double)(long long)acc[i] * inv);
+        const T v = poison ? T(NAN) : (T)((double)(long long)acc[i] * inv);
         out[i] = accumulate ? out[i] + v : v;
     }
 }

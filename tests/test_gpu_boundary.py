@@ -161,3 +161,35 @@ def test_sorted_plan_refuses_skipped_instances(ot, cfg1):
     assert e.value.code == -1
     # empty skipped instances are fine
     ot.BatchPlan(t, [0, 10, 10, 30], [7, 0, 7], dtype=torch.float32, mode="fixed", sort_points=True).close()
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_non_finite_force(ot, cfg1, bad):
+    """A force with a non-finite component: ATOMIC spreading carries it to the
+    leaves that point reaches (the oracle's non-finite leaves, and no others);
+    FIXED spreading, whose integer sums cannot carry it, returns NaN
+    everywhere, plain and batched (sorted or not)."""
+    w, o, t = cfg1
+    dtype = torch.float32
+    rng = np.random.default_rng(19)
+    pts = as_dtype(w.points, dtype)
+    frc = as_dtype(w.forces, dtype)
+    frc[123, 1] = bad
+    P, F = to_dev(pts, dtype), to_dev(frc, dtype)
+    a = t.spread(F, P, mode="atomic").cpu().numpy()
+    f = o.spread(frc, pts)
+    assert np.array_equal(~np.isfinite(a), ~np.isfinite(f))
+    assert (~np.isfinite(a)).sum() > 0 and np.isfinite(a).sum() > 0.99 * a.size
+    assert torch.isnan(t.spread(F, P, mode="fixed")).all()
+    n = P.shape[0]
+    for sort in (False, True):
+        plan = ot.BatchPlan(t, [0, 1000, n], [7, 7], dtype=dtype, mode="fixed", sort_points=sort)
+        fo = torch.zeros((t.n_leaves, 3), dtype=dtype, device="cuda")
+        plan.run(P, field=torch.zeros_like(fo), force=F, ids=torch.empty(n, dtype=torch.int32, device="cuda"),
+                 vel=torch.empty_like(P), field_out=fo)
+        torch.cuda.synchronize()
+        assert torch.isnan(fo).all()
+        plan.close()
+    # and a finite force field afterwards is clean again (the flag is per call)
+    frc2 = as_dtype(w.forces, dtype)
+    assert torch.isfinite(t.spread(to_dev(frc2, dtype), P, mode="fixed")).all()
