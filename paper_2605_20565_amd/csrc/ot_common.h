@@ -41,6 +41,12 @@ struct TreeView {
     int32_t nleaf;     // leaves (ids are 0 .. nleaf - 1)
     int32_t lev[kMaxTabLevels];   // cell level of each table level; lev[0] = root level
     int64_t off[kMaxTabLevels];   // entry offset of each level's pool; off[0] = 0
+    // The same pool offsets in device memory, after the table's entries.
+    // Kernels index them by a level number that varies by lane: a dynamic
+    // index into the by-value kernel argument above would put a copy of the
+    // whole struct in per-lane scratch memory.  Level t's cells are at level
+    // min(lev[0] + 3t, L), so lev[] itself is never indexed on the device.
+    const int64_t *pool_off;
 };
 
 // Spread the low 10 bits of v so that bit b lands on bit 3b.
@@ -93,20 +99,31 @@ __device__ __forceinline__ uint32_t ld_table(const TreeView &tv, int64_t i)
     return ((const __attribute__((address_space(1))) uint32_t *)tv.table)[i];
 }
 
+// Continue a descent from table entry e (of the root) down to the leaf
+// entry of the finest-level cell (ix, iy, iz).
+__device__ __forceinline__ uint32_t descend_below_root(const TreeView &tv, uint32_t e, uint32_t ix, uint32_t iy,
+                                                       uint32_t iz)
+{
+    int lv = tv.lev[0];
+    for (int t = 1; t < tv.nlev && (e & kSplit); ++t) {
+        const int nl = min(lv + 3, tv.L);
+        const int d = nl - lv, s = tv.L - nl;
+        const uint32_t m = (1u << d) - 1u;
+        const uint32_t sub = interleave3((ix >> s) & m, (iy >> s) & m, (iz >> s) & m);
+        const int64_t po = ((const __attribute__((address_space(1))) int64_t *)tv.pool_off)[t];
+        e = ld_table(tv, po + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
+        lv = nl;
+    }
+    return e;
+}
+
 // Table entry of the leaf containing the finest-level cell (ix, iy, iz).
 __device__ __forceinline__ uint32_t descend(const TreeView &tv, uint32_t ix, uint32_t iy,
                                             uint32_t iz)
 {
-    int sh = tv.L - tv.lev[0];
-    uint32_t e = ld_table(tv, interleave3(ix >> sh, iy >> sh, iz >> sh));
-    for (int t = 1; t < tv.nlev && (e & kSplit); ++t) {
-        int d = tv.lev[t] - tv.lev[t - 1];
-        int s = tv.L - tv.lev[t];
-        uint32_t m = (1u << d) - 1u;
-        uint32_t sub = interleave3((ix >> s) & m, (iy >> s) & m, (iz >> s) & m);
-        e = ld_table(tv, tv.off[t] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
-    }
-    return e;
+    const int sh = tv.L - tv.lev[0];
+    const uint32_t e = ld_table(tv, interleave3(ix >> sh, iy >> sh, iz >> sh));
+    return descend_below_root(tv, e, ix, iy, iz);
 }
 
 // Integer coordinates at level L: floor(x 2^L) in FP64, wrapped (periodic)

@@ -105,6 +105,9 @@ __device__ __forceinline__ void block_max_to(unsigned long long v, unsigned long
 // with the host's leaf entry (level << 26 | id); points without a host get
 // n_leaves.  Digits are taken from the id bits only.  Workgroup b covers the first
 // pass's tile b and leaves its digit counts in counts[d * nblocks + b].
+// A thread's kItems points go through the descent together: all positions,
+// then all root-table loads, then the deeper levels, so that the table loads
+// (the pass's latency) are in flight at once rather than one after another.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n, const T *__restrict__ pos,
                                                          int32_t *__restrict__ ids, uint64_t *__restrict__ kv,
@@ -115,18 +118,30 @@ __global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n,
     for (int i = threadIdx.x; i < kBuckets; i += kThreads) hist[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
-#pragma unroll 4
+    uint32_t I[kItems][3];
+    uint32_t e[kItems];
+    bool ok[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t k = base + j * kThreads + threadIdx.x;
+        ok[j] = k < n && point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I[j]);
+    }
+    const int sh = tv.L - tv.lev[0];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+        e[j] = ok[j] ? ld_table(tv, interleave3(I[j][0] >> sh, I[j][1] >> sh, I[j][2] >> sh)) : none;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+        if (e[j] & kSplit) e[j] = descend_below_root(tv, e[j], I[j][0], I[j][1], I[j][2]);
+#pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t k = base + j * kThreads + threadIdx.x;
         if (k < n) {
-            uint32_t I[3];
-            const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
             // the host's whole leaf entry (level << 26 | id): the tracking pass
             // takes it from here instead of searching again
-            const uint32_t e = ok ? descend(tv, I[0], I[1], I[2]) : none;
-            if (ids) ids[k] = ok ? (int32_t)(e & kIdMask) : -1;
-            kv[k] = ((uint64_t)e << 32) | (uint32_t)k;
-            atomicAdd(&hist[((e & kIdMask) >> shift) & (kBuckets - 1)], 1u);
+            if (ids) ids[k] = ok[j] ? (int32_t)(e[j] & kIdMask) : -1;
+            kv[k] = ((uint64_t)e[j] << 32) | (uint32_t)k;
+            atomicAdd(&hist[((e[j] & kIdMask) >> shift) & (kBuckets - 1)], 1u);
         }
     }
     __syncthreads();

@@ -34,19 +34,6 @@ struct FxWs {
 __device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-// Table entry below a SPLIT root entry: continue the descent at level 1.
-__device__ __forceinline__ uint32_t descend_below_root(const TreeView &tv, uint32_t e, uint32_t ix, uint32_t iy,
-                                                       uint32_t iz)
-{
-    for (int t = 1; t < tv.nlev && (e & kSplit); ++t) {
-        const int d = tv.lev[t] - tv.lev[t - 1];
-        const int s = tv.L - tv.lev[t];
-        const uint32_t m = (1u << d) - 1u;
-        const uint32_t sub = interleave3((ix >> s) & m, (iy >> s) & m, (iz >> s) & m);
-        e = ld_table(tv, tv.off[t] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub);
-    }
-    return e;
-}
 
 // Stencil of one point: host entry, 1-D weights, and per axis the three node
 // cells' centre coordinates at the finest level (N) and their root-table

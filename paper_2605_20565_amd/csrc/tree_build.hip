@@ -479,11 +479,14 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
         entries += (int64_t)hcnt[t - 1] << (3 * (tv.lev[t] - tv.lev[t - 1]));
     }
     if (entries >= (int64_t(1) << 40)) return fail(OT_ERR_CAPACITY, "ot_build_tree: descent table too large");
+    // the pool offsets follow the entries, 8-byte aligned
+    const int64_t off_at = (entries + 1) & ~int64_t(1);
     DevBuf table, flags, ids, stmp;
-    if ((rc = dalloc(table, entries * 4)) || (rc = dalloc(flags, n * 4)) || (rc = dalloc(ids, n * 4)) ||
+    if ((rc = dalloc(table, (off_at + 2 * kMaxTabLevels) * 4)) || (rc = dalloc(flags, n * 4)) || (rc = dalloc(ids, n * 4)) ||
         (rc = dalloc(stmp, scan_tmp_words(n) * 4)))
         return rc;
     hipLaunchKernelGGL(k_fill_u32, dim3(2048), dim3(256), 0, s, (uint32_t *)table.p, entries, 0xFFFFFFFFu);
+    OT_HIP(hipMemcpyAsync((uint32_t *)table.p + off_at, tv.off, sizeof(tv.off), hipMemcpyHostToDevice, s));
     for (int t = 0; t < tv.nlev; ++t) {
         if (t + 1 < tv.nlev) {
             hipLaunchKernelGGL(k_split_flags, dim3(nblk(n)), dim3(256), 0, s, ks, (const uint8_t *)lvs.p, n, L,
@@ -517,6 +520,7 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
     tr->table = (uint32_t *)table.release();
     tr->table_entries = entries;
     tv.table = tr->table;
+    tv.pool_off = (const int64_t *)(tr->table + off_at);
     tv.levels = tr->levels;
     tv.nleaf = (int32_t)n;
     tr->view = tv;
