@@ -188,16 +188,48 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     const int64_t base = (int64_t)tile * kTile;
     const int64_t rem = n - base;
     const int valid = rem < kTile ? (int)rem : kTile;
-    for (int d = threadIdx.x; d < kBuckets; d += kThreads) dcount[d] = 0;
-    __syncthreads();
-    // coalesced load of the tile's keys; padding sorts last
+    // The tile's words and records, read once in input order (coalesced) and
+    // before the ranking, so that their latency overlaps it.
+    T rv[kItems][R];
+    uint32_t lo[kItems], kk[kItems];
+    unsigned long long mx = 0;
+    bool bad = false;
+#pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int li = j * kThreads + threadIdx.x;
-        uint32_t key = 0xFFFFFFFFu;
+        lo[j] = 0u;
+        kk[j] = 0xFFFFFFFFu;   // padding sorts last
+#pragma unroll
+        for (int c = 0; c < R; ++c) rv[j][c] = T(0);
         if (li < valid) {
-            key = (uint32_t)(kin[base + li] >> 32);
-            atomicAdd(&dcount[((key & kIdMask) >> shift) & (kBuckets - 1)], 1u);
+            const int64_t src = base + li;
+            const uint64_t w = kin[src];
+            kk[j] = (uint32_t)(w >> 32);
+            lo[j] = (uint32_t)w;
+            if (rin) {
+#pragma unroll
+                for (int c = 0; c < R; ++c) rv[j][c] = rin[R * src + c];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) rv[j][c] = pos[3 * src + c];
+#pragma unroll
+                for (int c = 3; c < R; ++c) rv[j][c] = force[3 * src + (c - 3)];
+            }
+            if (maxbits) {
+#pragma unroll
+                for (int c = 3; c < R; ++c) {
+                    if (isfinite(rv[j][c])) mx = std::max(mx, abs_bits_of(rv[j][c]));
+                    else bad = true;
+                }
+            }
         }
+    }
+    for (int d = threadIdx.x; d < kBuckets; d += kThreads) dcount[d] = 0;
+    __syncthreads();
+    for (int j = 0; j < kItems; ++j) {
+        const int li = j * kThreads + threadIdx.x;
+        const uint32_t key = kk[j];
+        if (li < valid) atomicAdd(&dcount[((key & kIdMask) >> shift) & (kBuckets - 1)], 1u);
         sk[pad(li)] = key;
         si[pad(li)] = (uint16_t)li;
     }
@@ -254,37 +286,6 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     using Chunk = typename Chunk2<T, CW>::type;
     __shared__ Chunk stg[kPadded];
     __shared__ uint32_t slo[kPadded];
-    T rv[kItems][R];
-    uint32_t lo[kItems];
-    unsigned long long mx = 0;
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        const int li = j * kThreads + threadIdx.x;
-        lo[j] = 0u;
-#pragma unroll
-        for (int c = 0; c < R; ++c) rv[j][c] = T(0);
-        if (li < valid) {
-            const int64_t src = base + li;
-            lo[j] = (uint32_t)kin[src];
-            if (rin) {
-#pragma unroll
-                for (int c = 0; c < R; ++c) rv[j][c] = rin[R * src + c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) rv[j][c] = pos[3 * src + c];
-#pragma unroll
-                for (int c = 3; c < R; ++c) rv[j][c] = force[3 * src + (c - 3)];
-            }
-            if (maxbits) {
-#pragma unroll
-                for (int c = 3; c < R; ++c) {
-                    if (isfinite(rv[j][c])) mx = std::max(mx, abs_bits_of(rv[j][c]));
-                    else bad = true;
-                }
-            }
-        }
-    }
     // sorted position i = j * kThreads + thread: its destination and source slot
     int64_t dstv[kItems];
     int srcv[kItems];
