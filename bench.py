@@ -551,8 +551,25 @@ def particle_measure(w, tree, field, dev, dt, torch, timeit):
     ids = tree.locate(X)
     prm = dict(dt0=1e-3, r_p=1e-3, rho_p=2.5, rho_f=1.0, nu=1e-3, g=(0.0, 0.0, -1.0))
     tree.particle_step(field, X, V, VP, AP, ids, first=True, **prm)
+    n = int(X.shape[0])
+    # algorithmic bytes of a step: the four state arrays read and written, the
+    # new host ids written, every leaf's field row read once
+    nbytes = n * (8 * 3 * X.element_size() + 4) + field.numel() * field.element_size()
     ms = timeit(lambda: tree.particle_step(field, X, V, VP, AP, ids, **prm), 10)
-    return {"particles": int(X.shape[0]), "ms_per_step": round(ms, 4), "particles_per_s": X.shape[0] / (ms * 1e-3)}
+    # host-ordered state (ot_particle_sort), the layout a simulation keeps by
+    # re-sorting every few steps; the sort's own time is reported beside it
+    from paper_2605_20565_amd import lib as otlib
+    work = torch.empty(otlib.ot_particle_sort_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    outs = tuple(torch.empty_like(X) for _ in range(4))
+    ms_sort = timeit(lambda: tree.particle_sort(X, V, VP, AP, out=outs, work=work), 5)
+    Xs, Vs, VPs, APs, ids_s, _ = tree.particle_sort(X, V, VP, AP, out=outs, work=work)
+    ms_sorted = timeit(lambda: tree.particle_step(field, Xs, Vs, VPs, APs, ids_s, **prm), 10)
+    return {"particles": n, "ms_per_step": round(ms, 4), "particles_per_s": n / (ms * 1e-3),
+            "algorithmic_bytes_per_step": nbytes,
+            "hbm_frac": round(nbytes / (ms * 1e-3) / (HBM_PEAK_GBPS * 1e9), 4),
+            "host_ordered_ms_per_step": round(ms_sorted, 4),
+            "host_ordered_hbm_frac": round(nbytes / (ms_sorted * 1e-3) / (HBM_PEAK_GBPS * 1e9), 4),
+            "sort_ms": round(ms_sort, 4)}
 
 
 def backward_measure(w, tree, field, dev, dt, mode, ot, torch, timeit, per_body=125_000):

@@ -397,6 +397,26 @@ typedef struct {
 int ot_particle_step(const ot_tree *tree, const void *field, void *pos, void *vel, void *vel_prev,
                      void *acc_prev, int32_t *ids, int32_t dtype, int64_t n,
                      const ot_particle_params *params, void *stream);
+
+/* Host ordering of point particles: the particle state reordered by host
+ * leaf, i.e. in the Z-order of the leaves (Sec. 3.1), so that the particle
+ * step's node lookups and field reads of neighbouring particles share cache
+ * lines.  A simulation keeps its particles in this order and re-sorts every
+ * few steps (particles move by less than a cell per step, Sec. 2.3).
+ * Reads the (n, 3) dtype arrays pos, vel, vel_prev, acc_prev and writes them
+ * reordered to pos_out, vel_out, vel_prev_out, acc_prev_out (distinct from
+ * the inputs).  ids_out (n,) int32: the host leaf of each output row, -1 for
+ * a particle without one; perm_out (n,) int32: the input row of each output
+ * row; either may be NULL.  Stable: particles of one host keep their input
+ * order, particles without a host come last.  n < 2^31.  work: 256-byte
+ * aligned device buffer of ot_particle_sort_workspace_bytes(n) bytes, or
+ * NULL (allocated and freed on the stream).  The state is copied bit for
+ * bit.  Errors: OT_ERR_INVALID, OT_ERR_OOM, OT_ERR_HIP. */
+int64_t ot_particle_sort_workspace_bytes(int64_t n);
+int ot_particle_sort(const ot_tree *tree, int32_t dtype, int64_t n, const void *pos, const void *vel,
+                     const void *vel_prev, const void *acc_prev, void *pos_out, void *vel_out,
+                     void *vel_prev_out, void *acc_prev_out, int32_t *ids_out, int32_t *perm_out,
+                     void *work, void *stream);
 int ot_mdf(const ot_tree *tree, void *field, const void *pos, const void *target, int32_t dtype,
            int64_t n, int32_t n_iter, double dt, double rho, int32_t mode, void *force_lag,
            void *force_eul, void *work, void *stream);

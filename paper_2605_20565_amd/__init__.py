@@ -67,7 +67,7 @@ EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_g
            "ot_relocate", "ot_leaf_splitters", "ot_find_owner", "ot_particle_step", "ot_interp_backward",
            "ot_spread_backward", "ot_batch_run_grad", "ot_interp_grad_pos", "ot_spread_grad_pos",
            "ot_spread_workspace_bytes", "ot_batch_plan_windows", "ot_spread_noalloc", "ot_force_mean",
-           "ot_force_mean_workspace_bytes")
+           "ot_force_mean_workspace_bytes", "ot_particle_sort", "ot_particle_sort_workspace_bytes")
 
 
 def _load():
@@ -107,6 +107,7 @@ def _load():
         "ot_leaf_splitters": [P, i32, P, P],
         "ot_find_owner": [P, i32, i32, i32, P, i32, i64, P, P, P],
         "ot_particle_step": [P, P, P, P, P, P, P, i32, i64, ctypes.POINTER(ParticleParams), P],
+        "ot_particle_sort": [P, i32, i64, P, P, P, P, P, P, P, P, P, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -116,6 +117,8 @@ def _load():
     L.ot_mdf_workspace_bytes.restype = i64
     L.ot_spread_workspace_bytes.argtypes = [P]
     L.ot_spread_workspace_bytes.restype = i64
+    L.ot_particle_sort_workspace_bytes.argtypes = [i64]
+    L.ot_particle_sort_workspace_bytes.restype = i64
     L.ot_force_mean_workspace_bytes.argtypes = []
     L.ot_force_mean_workspace_bytes.restype = i64
     L.ot_strerror.argtypes = [i32]
@@ -467,6 +470,29 @@ class Tree:
                              (ctypes.c_double * 3)(*[float(x) for x in g]), int(bool(first)), 0)
         _check(lib.ot_particle_step(self._h, _ptr(field), _ptr(pos), _ptr(vel), _ptr(vel_prev), _ptr(acc_prev),
                                     _ptr(ids), _dtype_code(pos), pos.shape[0], ctypes.byref(prm), _stream()))
+
+    def particle_sort(self, pos: torch.Tensor, vel: torch.Tensor, vel_prev: torch.Tensor, acc_prev: torch.Tensor,
+                      out=None, work: Optional[torch.Tensor] = None):
+        """Particle state reordered by host leaf (ot_particle_sort): returns
+        (pos, vel, vel_prev, acc_prev, ids, perm), the four arrays reordered,
+        each row's host id (-1: none) and its input row.  `out`: four arrays
+        of the shape of pos to write into (not the inputs); `work`: a uint8
+        device buffer of ot_particle_sort_workspace_bytes(n) bytes."""
+        pos = _rows3(pos, "pos")
+        for name, tns in (("vel", vel), ("vel_prev", vel_prev), ("acc_prev", acc_prev)):
+            if tns.shape != pos.shape or tns.dtype != pos.dtype or not tns.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous (n, 3) tensor of the dtype of pos")
+        n = pos.shape[0]
+        if out is None:
+            out = tuple(torch.empty_like(pos) for _ in range(4))
+        if len(out) != 4 or any(o.shape != pos.shape or o.dtype != pos.dtype or not o.is_contiguous() for o in out):
+            raise ValueError("out must be four contiguous tensors shaped like pos")
+        ids = torch.empty(n, dtype=torch.int32, device=pos.device)
+        perm = torch.empty(n, dtype=torch.int32, device=pos.device)
+        _check(lib.ot_particle_sort(self._h, _dtype_code(pos), n, _ptr(pos), _ptr(vel), _ptr(vel_prev),
+                                    _ptr(acc_prev), *[_ptr(o) for o in out], _ptr(ids), _ptr(perm),
+                                    _ptr(work) if work is not None else None, _stream()))
+        return (*out, ids, perm)
 
     def mdf(self, field: torch.Tensor, pos: torch.Tensor, target: torch.Tensor, n_iter: int, dt: float = 1.0,
             rho: float = 1.0, mode: str = "fixed", inplace: bool = False,

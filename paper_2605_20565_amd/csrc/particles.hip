@@ -117,6 +117,48 @@ __global__ __launch_bounds__(256) void k_particle_step(TreeView tv, int l_min, i
     }
 }
 
+// Host ordering of point particles.  Sort key of each particle: its host
+// leaf id, or n_leaves when it has none (those go last); value: its index.
+template <typename T>
+__global__ __launch_bounds__(256) void k_particle_keys(TreeView tv, int64_t n, const T *__restrict__ pos,
+                                                       uint64_t *__restrict__ key, int32_t *__restrict__ val)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    uint32_t I[3];
+    const bool ok = point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I);
+    key[k] = ok ? (uint64_t)(descend(tv, I[0], I[1], I[2]) & kIdMask) : (uint64_t)tv.nleaf;
+    val[k] = (int32_t)k;
+}
+
+// Row i of the outputs is input row src[i] of each state array.
+template <typename T>
+__global__ __launch_bounds__(256) void k_particle_gather(int64_t n, const uint64_t *__restrict__ key,
+                                                         const int32_t *__restrict__ src, uint64_t nleaf,
+                                                         const T *__restrict__ pos, const T *__restrict__ vel,
+                                                         const T *__restrict__ vel_prev,
+                                                         const T *__restrict__ acc_prev, T *__restrict__ pos_o,
+                                                         T *__restrict__ vel_o, T *__restrict__ vel_prev_o,
+                                                         T *__restrict__ acc_prev_o, int32_t *__restrict__ ids_o,
+                                                         int32_t *__restrict__ perm_o)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = src[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        pos_o[3 * i + d] = pos[3 * j + d];
+        vel_o[3 * i + d] = vel[3 * j + d];
+        vel_prev_o[3 * i + d] = vel_prev[3 * j + d];
+        acc_prev_o[3 * i + d] = acc_prev[3 * j + d];
+    }
+    if (ids_o) ids_o[i] = key[i] < nleaf ? (int32_t)key[i] : -1;
+    if (perm_o) perm_o[i] = (int32_t)j;
+}
+
+// Workspace layout: two key and two value buffers, then the radix sort's.
+int64_t psort_align(int64_t b) { return (b + 255) & ~int64_t(255); }
+
 }  // namespace
 }  // namespace ot
 
@@ -149,5 +191,63 @@ extern "C" int ot_particle_step(const ot_tree *t, const void *field, void *pos, 
     }
 #undef OT_PSTEP
     OT_HIP(hipGetLastError());
+    return OT_OK;
+}
+
+extern "C" int64_t ot_particle_sort_workspace_bytes(int64_t n)
+{
+    if (n < 0) n = 0;
+    return 2 * psort_align(8 * n) + 2 * psort_align(4 * n) + psort_align(radix_ws_bytes(n));
+}
+
+extern "C" int ot_particle_sort(const ot_tree *t, int32_t dtype, int64_t n, const void *pos, const void *vel,
+                                const void *vel_prev, const void *acc_prev, void *pos_out, void *vel_out,
+                                void *vel_prev_out, void *acc_prev_out, int32_t *ids_out, int32_t *perm_out,
+                                void *work, void *stream)
+{
+    if (!t) return fail(OT_ERR_INVALID, "ot_particle_sort: tree is NULL");
+    if (dtype != OT_F32 && dtype != OT_F64) return fail(OT_ERR_INVALID, "dtype must be OT_F32 or OT_F64");
+    if (n < 0 || n > INT32_MAX) return fail(OT_ERR_INVALID, "ot_particle_sort: need 0 <= n < 2^31");
+    if (n > 0 && (!pos || !vel || !vel_prev || !acc_prev || !pos_out || !vel_out || !vel_prev_out || !acc_prev_out))
+        return fail(OT_ERR_INVALID, "ot_particle_sort: NULL array");
+    if ((uintptr_t)work & 255u) return fail(OT_ERR_INVALID, "ot_particle_sort: work must be 256-byte aligned");
+    if (n == 0) return OT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    void *owned = nullptr;
+    if (!work) {
+        if (hipMallocAsync(&owned, (size_t)ot_particle_sort_workspace_bytes(n), s) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(OT_ERR_OOM, "ot_particle_sort: workspace");
+        }
+        work = owned;
+    }
+    char *w = (char *)work;
+    uint64_t *k0 = (uint64_t *)w;
+    uint64_t *k1 = (uint64_t *)(w + psort_align(8 * n));
+    int32_t *v0 = (int32_t *)(w + 2 * psort_align(8 * n));
+    int32_t *v1 = (int32_t *)(w + 2 * psort_align(8 * n) + psort_align(4 * n));
+    void *rws = w + 2 * psort_align(8 * n) + 2 * psort_align(4 * n);
+    // keys span 0 .. n_leaves (n_leaves: no host)
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) <= t->n_leaves) ++bits;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    if (dtype == OT_F32)
+        hipLaunchKernelGGL(k_particle_keys<float>, g, b, 0, s, t->view, n, (const float *)pos, k0, v0);
+    else
+        hipLaunchKernelGGL(k_particle_keys<double>, g, b, 0, s, t->view, n, (const double *)pos, k0, v0);
+    uint64_t *ks = nullptr;
+    int32_t *vs = nullptr;
+    radix_sort_pairs(k0, v0, k1, v1, n, bits, rws, &ks, &vs, s);
+#define OT_PGATHER(TT)                                                                                           \
+    hipLaunchKernelGGL(k_particle_gather<TT>, g, b, 0, s, n, (const uint64_t *)ks, (const int32_t *)vs,          \
+                       (uint64_t)t->n_leaves, (const TT *)pos, (const TT *)vel, (const TT *)vel_prev,            \
+                       (const TT *)acc_prev, (TT *)pos_out, (TT *)vel_out, (TT *)vel_prev_out, (TT *)acc_prev_out, \
+                       ids_out, perm_out)
+    if (dtype == OT_F32) OT_PGATHER(float);
+    else OT_PGATHER(double);
+#undef OT_PGATHER
+    hipError_t e = hipGetLastError();
+    if (owned) (void)hipFreeAsync(owned, s);
+    if (e != hipSuccess) return hip_fail(e, "ot_particle_sort");
     return OT_OK;
 }

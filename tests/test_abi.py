@@ -87,6 +87,15 @@ def test_migration_host_side_validation(ot):
 def test_particle_step_host_side_validation(ot):
     L = ot.lib
     assert L.ot_particle_step(None, None, None, None, None, None, None, 0, 1, None, None) == -1
+    dummy = ctypes.c_void_p(0x1000)
+    args = [dummy] * 8
+    assert L.ot_particle_sort(None, 0, 10, *args, None, None, None, None) == -1
+    assert b"tree is NULL" in L.ot_last_error()
+    assert L.ot_particle_sort(dummy, 0, -1, *args, None, None, None, None) == -1
+    assert L.ot_particle_sort(dummy, 0, 10, *args, None, None, ctypes.c_void_p(0x1001), None) == -1
+    assert b"256-byte aligned" in L.ot_last_error()
+    assert L.ot_particle_sort(dummy, 0, 10, None, *args[1:], None, None, None, None) == -1
+    assert L.ot_particle_sort_workspace_bytes(1000) >= 1000 * 24
 
 
 def test_backward_host_side_validation(ot):
