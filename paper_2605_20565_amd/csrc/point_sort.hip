@@ -18,6 +18,8 @@
 // takes max |F| for the fixed-point scale, since it reads every force anyway.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ot_common.h"
 #include "point_sort.h"
 
@@ -49,6 +51,11 @@ template <typename T>
 struct Chunk2<T, 1> {
     using type = T;
     static __device__ __forceinline__ T pack(const T *v, int c) { return v[c]; }
+};
+
+// Four floats at a 4-byte aligned address (one 16-byte store).
+struct __attribute__((aligned(4))) F4u {
+    float x, y, z, w;
 };
 
 // LDS index with one pad word per 32: the blocked reads (stride kItems) and
@@ -282,10 +289,15 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     // from global memory instead, at its source inside the tile, fetched
     // about 4x its bytes past L2 and took 319 against 232 us per pass on
     // 10^7 points.)
+    // FP32 records of 6 values move as one 16-byte and one 8-byte chunk;
+    // otherwise in chunks of CW values
+    constexpr bool kF6 = std::is_same<T, float>::value && R == 6;
     constexpr int CW = (R % 2 == 0) ? 2 : 1;
-    using Chunk = typename Chunk2<T, CW>::type;
+    constexpr int kChunks = kF6 ? 2 : R / CW;
+    using Chunk = typename std::conditional<kF6, float4, typename Chunk2<T, CW>::type>::type;
     __shared__ Chunk stg[kPadded];
-    __shared__ uint32_t slo[kPadded];
+    // the words' low halves (input indices) travel in the second FP32 chunk
+    __shared__ uint32_t slo[kF6 ? 1 : kPadded];
     // sorted position i = j * kThreads + thread: its destination and source slot
     int64_t dstv[kItems];
     int srcv[kItems];
@@ -302,20 +314,38 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         }
     }
 #pragma unroll
-    for (int ch = 0; ch < R / CW; ++ch) {
+    for (int ch = 0; ch < kChunks; ++ch) {
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
             const int li = j * kThreads + threadIdx.x;
-            stg[pad(li)] = Chunk2<T, CW>::pack(rv[j], CW * ch);
-            if (ch == 0) slo[pad(li)] = lo[j];
+            if constexpr (kF6) {
+                const float *v = reinterpret_cast<const float *>(rv[j]);
+                stg[pad(li)] = ch == 0 ? make_float4(v[0], v[1], v[2], v[3])
+                                       : make_float4(v[4], v[5], __uint_as_float(lo[j]), 0.f);
+            } else {
+                stg[pad(li)] = Chunk2<T, CW>::pack(rv[j], CW * ch);
+                if (ch == 0) slo[pad(li)] = lo[j];
+            }
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
             if (dstv[j] < 0) continue;
             const int i = j * kThreads + threadIdx.x;
-            if (ch == 0) kout[dstv[j]] = ((uint64_t)sk[pad(i)] << 32) | slo[pad(srcv[j])];
-            reinterpret_cast<Chunk *>(rout)[(R * dstv[j]) / CW + ch] = stg[pad(srcv[j])];
+            if constexpr (kF6) {
+                // a record starts at 24 dst bytes: 8-byte aligned
+                const float4 c = stg[pad(srcv[j])];
+                float *dst = reinterpret_cast<float *>(rout) + 6 * dstv[j];
+                if (ch == 0) {
+                    *reinterpret_cast<F4u *>(dst) = F4u{c.x, c.y, c.z, c.w};
+                } else {
+                    *reinterpret_cast<float2 *>(dst + 4) = make_float2(c.x, c.y);
+                    kout[dstv[j]] = ((uint64_t)sk[pad(i)] << 32) | __float_as_uint(c.z);
+                }
+            } else {
+                if (ch == 0) kout[dstv[j]] = ((uint64_t)sk[pad(i)] << 32) | slo[pad(srcv[j])];
+                reinterpret_cast<Chunk *>(rout)[(R * dstv[j]) / CW + ch] = stg[pad(srcv[j])];
+            }
         }
         __syncthreads();
     }
