@@ -433,8 +433,13 @@ def workload3_measure(args, dev, ot, torch, timeit):
     ids = torch.empty(n, dtype=torch.int32, device=dev)
     vel = torch.empty_like(P)
     fo = torch.empty_like(U)
-    plan = ot.BatchPlan(tree, offs, [7] * (len(offs) - 1), dtype=torch.float32, mode="fixed", sort_points=True,
-                        host_major=args.host_major)
+    # the launch shape from the autotuner's sorted candidates, as for the headline step
+    from paper_2605_20565_amd import tune as tuner
+    ops = [7] * (len(offs) - 1)
+    cands = [c for c in tuner.default_candidates(n) if c.sort_points]
+    best, _ = tuner.tune(tree, offs, ops, P, U, F, torch.float32, "fixed", candidates=cands, reps=3, cache_path=None)
+    plan = ot.BatchPlan(tree, offs, ops, dtype=torch.float32, mode="fixed", sort_points=True, block=best.block,
+                        tile=best.tile, grid=best.grid, host_major=args.host_major)
     ms_b = timeit(lambda: plan.run(P, field=U, force=F, ids=ids, vel=vel, field_out=fo), 10)
     plan.close()
 
@@ -448,6 +453,7 @@ def workload3_measure(args, dev, ot, torch, timeit):
     out = {"leaves": int(tree.n_leaves), "points": int(n), "instances": len(offs) - 1,
            "batched_ms_per_step": round(ms_b, 4), "batched_points_per_s": n / (ms_b * 1e-3),
            "per_instance_launches_ms_per_step": round(ms_i, 4), "batched_speedup": round(ms_i / ms_b, 2),
+           "batched_shape": best.label(),
            "touched_leaves": touched, "batched_roofline": _roof(n, touched, ms_b, "f32"),
            "path": "batched persistent kernel, HIP graph, in-step sort; FP32, FIXED"}
     tree.close()
@@ -667,10 +673,16 @@ def mdf_measure(w, tree, field, dev, dt, mode, torch, timeit, n_iter=5):
     offs = np.concatenate([[0], np.cumsum([w.instances[i + 1] - w.instances[i] for i in idx])])
     cen = torch.tensor([w.spheres[i].centre for i in range(len(idx))], dtype=dt, device=dev)
     us = timeit(lambda: ot.body_sums(f_lag, P, offs, cen, 1.0), 20) * 1e3
+    # the mean IBM force over the domain, subtracted from the leaf force field
+    # (deterministic FP64 reduction over all leaves, then the subtraction)
+    _, _, f_eul = tree.mdf(u, P, tgt, n_iter, mode=mode, work=work)
+    fm_work = torch.empty(ot.lib.ot_force_mean_workspace_bytes(), dtype=torch.uint8, device=dev)
+    us_mean = timeit(lambda: tree.force_mean(f_eul, subtract=True, work=fm_work), 20) * 1e3
     return {"markers": int(P.shape[0]), "iterations": n_iter, "ms_per_step": round(ms, 4),
             "ms_per_iteration": round(ms / n_iter, 4), "graph_replay_ms_per_step": round(ms_graph, 4),
             "spread_mode": mode,
-            "body_force_torque_us": round(us, 1), "bodies": len(idx)}
+            "body_force_torque_us": round(us, 1), "bodies": len(idx),
+            "force_mean_subtract_us": round(us_mean, 1), "leaves": int(tree.n_leaves)}
 
 
 def tree_mdf_bytes(tree, P):
