@@ -127,7 +127,9 @@ typedef struct {
 
 /* Tuning of the batched persistent pass.  Zero fields take defaults: 256
  * threads and 4 points per thread, narrowed (down to 64 threads, 1 point
- * per thread) when the run has too few points for two workgroups per CU. */
+ * per thread) when the run has too few points for two workgroups per CU;
+ * sorted plans take tiles of about 160 x (points per leaf), the nearest
+ * power of two between 1 and 4 points per thread. */
 typedef struct {
     int32_t block;        /* threads per workgroup (multiple of 64, <= 512)           */
     int32_t tile;         /* points per tile (multiple of block)                      */
