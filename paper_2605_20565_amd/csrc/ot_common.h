@@ -99,13 +99,31 @@ __device__ __forceinline__ uint32_t ld_table(const TreeView &tv, int64_t i)
     return ((const __attribute__((address_space(1))) uint32_t *)tv.table)[i];
 }
 
-// Continue a descent from table entry e (of the root) down to the leaf
-// entry of the finest-level cell (ix, iy, iz).
-__device__ __forceinline__ uint32_t descend_below_root(const TreeView &tv, uint32_t e, uint32_t ix, uint32_t iy,
-                                                       uint32_t iz)
+// Index of the level-1 pool entry below root entry e for the finest-level
+// cell (ix, iy, iz), or 0 when e is a leaf: callers issue many of these
+// loads at once, at valid addresses and without branches, and keep the
+// loaded entry only where e was split.  The level-1 pool offset is read at
+// a constant index of the tree view (a scalar kernel argument).
+__device__ __forceinline__ int64_t step1_index(const TreeView &tv, uint32_t e, uint32_t ix, uint32_t iy, uint32_t iz)
 {
-    int lv = tv.lev[0];
-    for (int t = 1; t < tv.nlev && (e & kSplit); ++t) {
+    const int l0 = tv.lev[0];
+    const int l1 = min(l0 + 3, tv.L);
+    const int d = l1 - l0, s = tv.L - l1;
+    const uint32_t m = (1u << d) - 1u;
+    const uint32_t sub = interleave3((ix >> s) & m, (iy >> s) & m, (iz >> s) & m);
+    return (e & kSplit) ? tv.off[1] + (int64_t)(e & ~kSplit) * (int64_t(1) << (3 * d)) + sub : int64_t(0);
+}
+
+// Continue a descent from a level-1 table entry e down to the leaf entry of
+// the finest-level cell (ix, iy, iz) (trees more than 3 levels deeper than
+// the root).  The level of each table step is computed and its pool offset
+// read from device memory: a lane-dependent index into the by-value tree
+// view would put a copy of the struct in per-lane scratch memory.
+__device__ __forceinline__ uint32_t descend_from_level2(const TreeView &tv, uint32_t e, uint32_t ix, uint32_t iy,
+                                                        uint32_t iz)
+{
+    int lv = min(tv.lev[0] + 3, tv.L);
+    for (int t = 2; t < tv.nlev && (e & kSplit); ++t) {
         const int nl = min(lv + 3, tv.L);
         const int d = nl - lv, s = tv.L - nl;
         const uint32_t m = (1u << d) - 1u;
@@ -115,6 +133,16 @@ __device__ __forceinline__ uint32_t descend_below_root(const TreeView &tv, uint3
         lv = nl;
     }
     return e;
+}
+
+// Continue a descent from root entry e down to the leaf entry of the
+// finest-level cell (ix, iy, iz).
+__device__ __forceinline__ uint32_t descend_below_root(const TreeView &tv, uint32_t e, uint32_t ix, uint32_t iy,
+                                                       uint32_t iz)
+{
+    if (!(e & kSplit)) return e;
+    e = ld_table(tv, step1_index(tv, e, ix, iy, iz));
+    return (e & kSplit) ? descend_from_level2(tv, e, ix, iy, iz) : e;
 }
 
 // Table entry of the leaf containing the finest-level cell (ix, iy, iz).

@@ -71,9 +71,15 @@ __global__ __launch_bounds__(256) void k_particle_step(TreeView tv, int l_min, i
             // a node outside the walls is dropped with its weight
             ent[q] = in ? ld_table(tv, interleave3(nc[q][0] >> rsh, nc[q][1] >> rsh, nc[q][2] >> rsh)) : 0u;
         }
+        // the level-1 step of every split node at once, then deeper levels (rare)
+        uint32_t e1[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (ent[q] & kSplit) ent[q] = descend_below_root(tv, ent[q], nc[q][0], nc[q][1], nc[q][2]);
+        for (int q = 0; q < 8; ++q) e1[q] = ld_table(tv, step1_index(tv, ent[q], nc[q][0], nc[q][1], nc[q][2]));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (ent[q] & kSplit) ent[q] = e1[q];
+            if (ent[q] & kSplit) ent[q] = descend_from_level2(tv, ent[q], nc[q][0], nc[q][1], nc[q][2]);
+        }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             if (!((inside >> q) & 1u)) continue;

@@ -128,18 +128,36 @@ __global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n,
     uint32_t I[kItems][3];
     uint32_t e[kItems];
     bool ok[kItems];
+    // loads at clamped indices, so that no item's load sits behind a branch
+    // (a load inside a branch is waited for at the branch's end)
+    T X[kItems][3];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t k = base + j * kThreads + threadIdx.x;
-        ok[j] = k < n && point_cell<T>(tv, pos[3 * k], pos[3 * k + 1], pos[3 * k + 2], I[j]);
+        const int64_t kc = k < n ? k : n - 1;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) X[j][d] = pos[3 * kc + d];
     }
     const int sh = tv.L - tv.lev[0];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j)
-        e[j] = ok[j] ? ld_table(tv, interleave3(I[j][0] >> sh, I[j][1] >> sh, I[j][2] >> sh)) : none;
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t k = base + j * kThreads + threadIdx.x;
+        ok[j] = point_cell<T>(tv, X[j][0], X[j][1], X[j][2], I[j]) && k < n;
+        const uint32_t r = ok[j] ? interleave3(I[j][0] >> sh, I[j][1] >> sh, I[j][2] >> sh) : 0u;
+        e[j] = ld_table(tv, r);
+    }
 #pragma unroll
     for (int j = 0; j < kItems; ++j)
-        if (e[j] & kSplit) e[j] = descend_below_root(tv, e[j], I[j][0], I[j][1], I[j][2]);
+        if (!ok[j]) e[j] = none;
+    // the level-1 step of every split entry at once, then deeper levels (rare)
+    uint32_t e1[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) e1[j] = ld_table(tv, step1_index(tv, e[j], I[j][0], I[j][1], I[j][2]));
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        if (e[j] & kSplit) e[j] = e1[j];
+        if (e[j] & kSplit) e[j] = descend_from_level2(tv, e[j], I[j][0], I[j][1], I[j][2]);
+    }
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t k = base + j * kThreads + threadIdx.x;

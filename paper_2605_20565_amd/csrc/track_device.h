@@ -320,25 +320,54 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
         make_stencil<T, PER>(tv, X, I, e, st);
         // phase 1: root-table entries of the 27 nodes (independent loads);
         // nodes dropped at a non-periodic wall are not looked up
+        // All 26 loads are issued before any result is used (a node dropped
+        // at a wall loads entry 0 and is then zeroed): the scheduler had
+        // interleaved their uses and waited after every eight.
         uint32_t ent[27];
 #pragma unroll
         for (int q = 0; q < 27; ++q) {
             const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+            if (q == 13) continue;
             const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
-            if (q == 13) ent[q] = st.host | ((uint32_t)st.level << kLevelShift);
-            else if (!PER && (st.valid & need) != need) ent[q] = 0u;
-            else ent[q] = ld_table(tv, st.R[0][ox] | (st.R[1][oy] << 1) | (st.R[2][oz] << 2));
+            const bool use = PER || (st.valid & need) == need;
+            ent[q] = ld_table(tv, use ? (st.R[0][ox] | (st.R[1][oy] << 1) | (st.R[2][oz] << 2)) : 0u);
         }
-        // phase 2: nodes inside split root cells continue the descent (rare)
+        __builtin_amdgcn_sched_barrier(0);
+        ent[13] = st.host | ((uint32_t)st.level << kLevelShift);
+        if (!PER) {
+#pragma unroll
+            for (int q = 0; q < 27; ++q) {
+                const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+                const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
+                if (q != 13 && (st.valid & need) != need) ent[q] = 0u;
+            }
+        }
+        // phase 2: nodes inside split root cells continue the descent, the
+        // level-1 step of all of them at once
         uint32_t any = 0u;
 #pragma unroll
         for (int q = 0; q < 27; ++q) any |= ent[q];
         if (any & kSplit) {
+            uint32_t sub[27];
 #pragma unroll
             for (int q = 0; q < 27; ++q) {
-                if (ent[q] & kSplit) {
-                    const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
-                    ent[q] = descend_below_root(tv, ent[q], st.N[0][ox], st.N[1][oy], st.N[2][oz]);
+                const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+                sub[q] = ld_table(tv, step1_index(tv, ent[q], st.N[0][ox], st.N[1][oy], st.N[2][oz]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            any = 0u;
+#pragma unroll
+            for (int q = 0; q < 27; ++q) {
+                if (ent[q] & kSplit) ent[q] = sub[q];
+                any |= ent[q];
+            }
+            if (any & kSplit) {   // trees more than 3 levels below the root
+#pragma unroll
+                for (int q = 0; q < 27; ++q) {
+                    if (ent[q] & kSplit) {
+                        const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
+                        ent[q] = descend_from_level2(tv, ent[q], st.N[0][ox], st.N[1][oy], st.N[2][oz]);
+                    }
                 }
             }
         }
