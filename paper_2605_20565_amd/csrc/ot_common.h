@@ -155,24 +155,26 @@ __device__ __forceinline__ uint32_t descend(const TreeView &tv, uint32_t ix, uin
 }
 
 // Integer coordinates at level L: floor(x 2^L) in FP64, wrapped (periodic)
-// or range-checked.  False when the point has no host cell.
+// or range-checked.  False when the point has no host cell.  Branch-free:
+// the periodic wrap is the floor-mod f - floor(f 2^-L) 2^L, exact in FP64
+// for |f| < 2^52, so no 64-bit integer conversion is needed, and the axes'
+// checks combine without short-circuits (which had compiled to a branch and
+// an exec-mask update per test).
 template <typename T>
 __device__ __forceinline__ bool point_cell(const TreeView &tv, T x, T y, T z, uint32_t I[3])
 {
     const double sc = (double)(int64_t(1) << tv.L);
-    const int64_t M = int64_t(1) << tv.L;
-    double v[3] = {(double)x * sc, (double)y * sc, (double)z * sc};
+    const double inv = 1.0 / sc;   // a power of two: exact
+    const double v[3] = {(double)x * sc, (double)y * sc, (double)z * sc};
     bool ok = true;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        ok = ok && (fabs(v[d]) < 4503599627370496.0);   // 2^52; false for NaN
-        int64_t c = ok ? (int64_t)floor(v[d]) : 0;
-        if (tv.periodic) {
-            c &= (M - 1);                                 // floor-mod for two's complement
-        } else {
-            ok = ok && (c >= 0) && (c < M);
-        }
-        I[d] = (uint32_t)c;
+        const bool fin = fabs(v[d]) < 4503599627370496.0;   // 2^52; false for NaN
+        double f = floor(fin ? v[d] : 0.0);
+        if (tv.periodic) f -= floor(f * inv) * sc;          // floor-mod into [0, 2^L)
+        const bool in = fin & (f >= 0.0) & (f < sc);
+        ok = ok & in;
+        I[d] = in ? (uint32_t)f : 0u;
     }
     return ok;
 }
