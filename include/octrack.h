@@ -407,7 +407,7 @@ int ot_particle_step(const ot_tree *tree, const void *field, void *pos, void *ve
  * few steps (particles move by less than a cell per step, Sec. 2.3).
  * Reads the (n, 3) dtype arrays pos, vel, vel_prev, acc_prev and writes them
  * reordered to pos_out, vel_out, vel_prev_out, acc_prev_out (distinct from
- * the inputs).  ids_out (n,) int32: the host leaf of each output row, -1 for
+ * the inputs and from each other: OT_ERR_INVALID otherwise).  ids_out (n,) int32: the host leaf of each output row, -1 for
  * a particle without one; perm_out (n,) int32: the input row of each output
  * row; either may be NULL.  Stable: particles of one host keep their input
  * order, particles without a host come last.  n < 2^31.  work: 256-byte

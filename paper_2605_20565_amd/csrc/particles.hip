@@ -217,6 +217,15 @@ extern "C" int ot_particle_sort(const ot_tree *t, int32_t dtype, int64_t n, cons
     if (n > 0 && (!pos || !vel || !vel_prev || !acc_prev || !pos_out || !vel_out || !vel_prev_out || !acc_prev_out))
         return fail(OT_ERR_INVALID, "ot_particle_sort: NULL array");
     if ((uintptr_t)work & 255u) return fail(OT_ERR_INVALID, "ot_particle_sort: work must be 256-byte aligned");
+    {
+        const void *in[4] = {pos, vel, vel_prev, acc_prev};
+        const void *out_[4] = {pos_out, vel_out, vel_prev_out, acc_prev_out};
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b)
+                if (n > 0 && (out_[a] == in[b] || (a < b && out_[a] == out_[b])))
+                    return fail(OT_ERR_INVALID, "ot_particle_sort: the output arrays must be distinct from each other "
+                                                "and from the inputs");
+    }
     if (n == 0) return OT_OK;
     hipStream_t s = (hipStream_t)stream;
     void *owned = nullptr;

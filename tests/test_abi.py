@@ -96,6 +96,11 @@ def test_particle_step_host_side_validation(ot):
     assert b"256-byte aligned" in L.ot_last_error()
     assert L.ot_particle_sort(dummy, 0, 10, None, *args[1:], None, None, None, None) == -1
     assert L.ot_particle_sort_workspace_bytes(1000) >= 1000 * 24
+    # an output that is also an input (or another output) is refused
+    d2 = [ctypes.c_void_p(0x1000 + 0x100 * i) for i in range(8)]
+    assert L.ot_particle_sort(dummy, 0, 10, *d2[:4], d2[0], *d2[5:], None, None, None, None) == -1
+    assert b"distinct" in L.ot_last_error()
+    assert L.ot_particle_sort(dummy, 0, 10, *d2[:4], d2[4], d2[4], *d2[6:], None, None, None, None) == -1
 
 
 def test_backward_host_side_validation(ot):
