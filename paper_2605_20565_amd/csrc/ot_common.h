@@ -47,6 +47,11 @@ struct TreeView {
     // whole struct in per-lane scratch memory.  Level t's cells are at level
     // min(lev[0] + 3t, L), so lev[] itself is never indexed on the device.
     const int64_t *pool_off;
+    // Root summary one level up (NULL when the root is level 0): entry m is
+    // the leaf entry of the first of the 8 root cells of level-(lev[0]-1)
+    // cell m when all 8 are leaves of level lev[0] (then child c's leaf is
+    // entry + c), kSplit otherwise.
+    const uint32_t *summary;
 };
 
 // Spread the low 10 bits of v so that bit b lands on bit 3b.
@@ -145,12 +150,25 @@ __device__ __forceinline__ uint32_t descend_below_root(const TreeView &tv, uint3
     return (e & kSplit) ? descend_from_level2(tv, e, ix, iy, iz) : e;
 }
 
+__device__ __forceinline__ uint32_t ld_summary(const TreeView &tv, uint32_t m)
+{
+    return ((const __attribute__((address_space(1))) uint32_t *)tv.summary)[m];
+}
+
 // Table entry of the leaf containing the finest-level cell (ix, iy, iz).
+// Points in random order look up the root summary first: a root an eighth
+// the size, which one XCD's L2 holds; only cells whose 8 root children are
+// not all root-level leaves continue to the root itself.
 __device__ __forceinline__ uint32_t descend(const TreeView &tv, uint32_t ix, uint32_t iy,
                                             uint32_t iz)
 {
     const int sh = tv.L - tv.lev[0];
-    const uint32_t e = ld_table(tv, interleave3(ix >> sh, iy >> sh, iz >> sh));
+    const uint32_t root = interleave3(ix >> sh, iy >> sh, iz >> sh);
+    if (tv.summary) {
+        const uint32_t sm = ld_summary(tv, root >> 3);
+        if (!(sm & kSplit)) return sm + (root & 7u);
+    }
+    const uint32_t e = ld_table(tv, root);
     return descend_below_root(tv, e, ix, iy, iz);
 }
 

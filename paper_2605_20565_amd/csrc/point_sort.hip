@@ -139,16 +139,23 @@ __global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n,
         for (int d = 0; d < 3; ++d) X[j][d] = pos[3 * kc + d];
     }
     const int sh = tv.L - tv.lev[0];
+    // root summary first (small enough for L2); the root itself only where
+    // the summary has no answer (other lanes load entry 0)
+    uint32_t root[kItems], sm[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t k = base + j * kThreads + threadIdx.x;
         ok[j] = point_cell<T>(tv, X[j][0], X[j][1], X[j][2], I[j]) && k < n;
-        const uint32_t r = ok[j] ? interleave3(I[j][0] >> sh, I[j][1] >> sh, I[j][2] >> sh) : 0u;
-        e[j] = ld_table(tv, r);
+        root[j] = ok[j] ? interleave3(I[j][0] >> sh, I[j][1] >> sh, I[j][2] >> sh) : 0u;
+        sm[j] = tv.summary ? ld_summary(tv, root[j] >> 3) : kSplit;
     }
 #pragma unroll
-    for (int j = 0; j < kItems; ++j)
+    for (int j = 0; j < kItems; ++j) e[j] = ld_table(tv, (sm[j] & kSplit) ? root[j] : 0u);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        if (!(sm[j] & kSplit)) e[j] = sm[j] + (root[j] & 7u);
         if (!ok[j]) e[j] = none;
+    }
     // the level-1 step of every split entry at once, then deeper levels (rare)
     uint32_t e1[kItems];
 #pragma unroll

@@ -341,6 +341,23 @@ __global__ void k_write_level(const uint64_t *__restrict__ keys, const uint8_t *
     }
 }
 
+// Summary of the root one level up: entry m describes the 8 root cells of
+// the level-(r-1) cell m.  When all 8 are leaves of level r, they are 8
+// consecutive leaves in Z-order and the entry is the first one's (so the
+// leaf of child c is entry + c); otherwise it is kSplit.
+__global__ void k_root_summary(const uint32_t *__restrict__ root, int64_t m_cells, int r, uint32_t *__restrict__ sum)
+{
+    const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (m >= m_cells) return;
+    bool uniform = true;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint32_t e = root[8 * m + c];
+        uniform = uniform && !(e & kSplit) && (int)((e >> kLevelShift) & 31u) == r;
+    }
+    sum[m] = uniform ? root[8 * m] : kSplit;
+}
+
 __global__ void k_count_value(const uint32_t *__restrict__ p, int64_t n, uint32_t v, unsigned *__restrict__ out)
 {
     unsigned c = 0;
@@ -479,10 +496,14 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
         entries += (int64_t)hcnt[t - 1] << (3 * (tv.lev[t] - tv.lev[t - 1]));
     }
     if (entries >= (int64_t(1) << 40)) return fail(OT_ERR_CAPACITY, "ot_build_tree: descent table too large");
-    // the pool offsets follow the entries, 8-byte aligned
+    // the pool offsets follow the entries, 8-byte aligned, then the root's
+    // summary one level up (an eighth of the root: most lookups of points in
+    // random order then hit a table small enough for one XCD's L2)
     const int64_t off_at = (entries + 1) & ~int64_t(1);
+    const int64_t sum_at = off_at + 2 * kMaxTabLevels;
+    const int64_t sum_cells = tv.lev[0] >= 1 ? (int64_t(1) << (3 * (tv.lev[0] - 1))) : 0;
     DevBuf table, flags, ids, stmp;
-    if ((rc = dalloc(table, (off_at + 2 * kMaxTabLevels) * 4)) || (rc = dalloc(flags, n * 4)) || (rc = dalloc(ids, n * 4)) ||
+    if ((rc = dalloc(table, (sum_at + sum_cells) * 4)) || (rc = dalloc(flags, n * 4)) || (rc = dalloc(ids, n * 4)) ||
         (rc = dalloc(stmp, scan_tmp_words(n) * 4)))
         return rc;
     hipLaunchKernelGGL(k_fill_u32, dim3(2048), dim3(256), 0, s, (uint32_t *)table.p, entries, 0xFFFFFFFFu);
@@ -496,6 +517,9 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
         hipLaunchKernelGGL(k_write_level, dim3(nblk(n)), dim3(256), 0, s, ks, (const uint8_t *)lvs.p, n, tv,
                            (uint32_t *)table.p, t, (const uint32_t *)ids.p);
     }
+    if (sum_cells)
+        hipLaunchKernelGGL(k_root_summary, dim3(nblk(sum_cells)), dim3(256), 0, s, (const uint32_t *)table.p, sum_cells,
+                           tv.lev[0], (uint32_t *)table.p + sum_at);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, (uint32_t *)scratch.p, (int64_t)1, 0u);
     hipLaunchKernelGGL(k_count_value, dim3(1024), dim3(256), 0, s, (const uint32_t *)table.p, entries, 0xFFFFFFFFu, err);
     OT_HIP(hipGetLastError());
@@ -521,6 +545,7 @@ extern "C" int ot_build_tree(const uint64_t *keys, const uint8_t *levels, int64_
     tr->table_entries = entries;
     tv.table = tr->table;
     tv.pool_off = (const int64_t *)(tr->table + off_at);
+    tv.summary = sum_cells ? tr->table + sum_at : nullptr;
     tv.levels = tr->levels;
     tv.nleaf = (int32_t)n;
     tr->view = tv;
