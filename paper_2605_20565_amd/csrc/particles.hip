@@ -45,11 +45,12 @@ __global__ __launch_bounds__(256) void k_particle_step(TreeView tv, int l_min, i
             i0[d] = (int64_t)f;
             t[d] = (T)(s - f);
         }
-        // the 8 nodes: root-table entries issued together, the deeper descent
-        // only under split root cells, then the gathers (independent loads
-        // instead of one search after another)
+        // the 8 nodes: root-summary entries issued together, root entries
+        // where the summary has no answer, the deeper descent only under
+        // split root cells, then the gathers (independent loads instead of
+        // one search after another)
         uint32_t nc[8][3];
-        uint32_t ent[8];
+        uint32_t ent[8], root[8], sm[8];
         T wq[8];
         uint32_t inside = 0u;
         const int rsh = tv.L - tv.lev[0];
@@ -68,8 +69,18 @@ __global__ __launch_bounds__(256) void k_particle_step(TreeView tv, int l_min, i
             }
             wq[q] = w;
             inside |= (in ? 1u : 0u) << q;
-            // a node outside the walls is dropped with its weight
-            ent[q] = in ? ld_table(tv, interleave3(nc[q][0] >> rsh, nc[q][1] >> rsh, nc[q][2] >> rsh)) : 0u;
+            // a node outside the walls is dropped with its weight; its lookups
+            // go to entry 0
+            root[q] = in ? interleave3(nc[q][0] >> rsh, nc[q][1] >> rsh, nc[q][2] >> rsh) : 0u;
+            sm[q] = tv.summary ? ld_summary(tv, root[q] >> 3) : kSplit;
+        }
+        // the root itself only where the summary has no answer
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ent[q] = ld_table(tv, (sm[q] & kSplit) ? root[q] : 0u);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (!(sm[q] & kSplit)) ent[q] = sm[q] + (root[q] & 7u);
+            if (!((inside >> q) & 1u)) ent[q] = 0u;
         }
         // the level-1 step of every split node at once, then deeper levels (rare)
         uint32_t e1[8];
