@@ -566,14 +566,15 @@ __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, i
     for (;;) {
         const int64_t kn = k + blockDim.x;
         const bool more = kn < end;
-        uint64_t wn = 0ull;
-        T Xn[3] = {T(0), T(0), T(0)};
-        if (more) {
-            wn = kv[kn];
-            Xn[0] = pos[(int64_t)rs * kn];
-            Xn[1] = pos[(int64_t)rs * kn + 1];
-            Xn[2] = pos[(int64_t)rs * kn + 2];
-        }
+        // unconditional loads (the last point reloads itself): a load
+        // inside a branch is waited for where the branch joins, which had
+        // made the prefetch wait before the current point's work
+        const int64_t kc = more ? kn : k;
+        const uint64_t wn = kv[kc];
+        T Xn[3];
+        Xn[0] = pos[(int64_t)rs * kc];
+        Xn[1] = pos[(int64_t)rs * kc + 1];
+        Xn[2] = pos[(int64_t)rs * kc + 2];
         track_point_at<T, OPS, PER, Sink>(tv, k, true, w, X, rs, field, force, ids, vel, sink, grad, nullptr);
         if (!more) break;
         k = kn;
