@@ -75,16 +75,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# The sources the measured step is built from (the batched pass, the point
-# sort, the per-point code and the spreading prologue/epilogue): a stored
-# traffic record applies while they are unchanged.
-STEP_SOURCES = ("batch.hip", "point_sort.hip", "point_sort.h", "track.hip", "track_device.h", "ot_common.h")
-
-
+# The library's sources and its build flags: a stored traffic record applies
+# while they are unchanged.
 def kernel_source_hash() -> str:
+    import glob
     h = hashlib.sha256()
-    for name in STEP_SOURCES + ("../../include/octrack.h",):
-        p = os.path.normpath(os.path.join(ROOT, "paper_2605_20565_amd", "csrc", name))
+    pkg = os.path.join(ROOT, "paper_2605_20565_amd")
+    files = sorted(glob.glob(os.path.join(pkg, "csrc", "*.hip")) + glob.glob(os.path.join(pkg, "csrc", "*.h")))
+    for p in files + [os.path.join(pkg, "build.py"), os.path.join(ROOT, "include", "octrack.h")]:
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode())
             h.update(f.read())
