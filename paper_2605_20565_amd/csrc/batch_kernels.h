@@ -101,11 +101,14 @@ int enqueue(ot_batch_plan *p, const void *field, const void *force, const void *
     const int64_t n = p->n_points;
     // counter[0]: the pass's tile queue, [1]: the per-point pass over handed-over
     // windows, [2]: how many windows were handed over
-    hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, p->counter, (int64_t)3, 0u);
     int rc;
     const bool spread = (p->ops_union & kOpSpread) != 0;
     const FxWs ws = fx_ws(p->fxws);
-    if (spread && (rc = spread_begin(t, ws, p->dtype, p->mode, 0, fout, s))) return rc;
+    if (spread) {
+        if ((rc = spread_begin(t, ws, p->dtype, p->mode, 0, fout, s, p->counter, 3))) return rc;
+    } else {
+        hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, p->counter, (int64_t)3, 0u);
+    }
     const uint64_t *kv = nullptr;
     int rs = 3;
     int32_t *kids = ids;

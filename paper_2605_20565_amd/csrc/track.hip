@@ -25,7 +25,23 @@ constexpr int kMaxPointsPerThread = 4;
 
 // Prepare the spreading target before a pass: zero the output (atomic mode,
 // overwrite) or the fixed-point accumulators and compute the scale.
-int spread_begin(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s)
+namespace {
+
+// Zero n 64-bit words at a and, in block 0, m 32-bit words at b: one launch
+// for the fixed-point workspace (its header first, then the accumulators)
+// and a batch plan's counters.
+__global__ void k_zero2(unsigned long long *__restrict__ a, int64_t n, unsigned *__restrict__ b, int64_t m)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0ull;
+    if (b && blockIdx.x == 0)
+        for (int64_t i = threadIdx.x; i < m; i += blockDim.x) b[i] = 0u;
+}
+
+}  // namespace
+
+int spread_begin(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s,
+                 unsigned *counters, int64_t n_counters)
 {
     const int64_t n3 = t->n_leaves * 3;
     if (mode == OT_SPREAD_ATOMIC) {
@@ -33,10 +49,12 @@ int spread_begin(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accu
             if (dtype == OT_F32) hipLaunchKernelGGL(k_fill<float>, dim3(1024), dim3(256), 0, s, (float *)fout, n3, 0.0f);
             else hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, (double *)fout, n3, 0.0);
         }
+        if (counters) hipLaunchKernelGGL(k_fill<unsigned>, dim3(1), dim3(64), 0, s, counters, n_counters, 0u);
     } else {
-        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1024), dim3(256), 0, s, ws.acc, n3, 0ull);
-        // max |F| and the non-finite flag
-        hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(1), dim3(64), 0, s, &ws.fx->maxbits, (int64_t)2, 0ull);
+        // the whole header (max |F|, the non-finite flag; the scale is set
+        // later) and the accumulators after it, and the counters
+        hipLaunchKernelGGL(k_zero2, dim3(1024), dim3(256), 0, s, (unsigned long long *)ws.fx,
+                           kFxHeader / 8 + n3, counters, n_counters);
     }
     OT_HIP(hipGetLastError());
     return OT_OK;

@@ -601,7 +601,9 @@ constexpr int kSmallSlots = 512;
 // the workspace's accumulators, take the fixed-point scale (max |F| over
 // `force` unless the caller already maxed it into ws.fx), and convert the
 // accumulators into field_out.
-int spread_begin(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
+// counters (optional): 32-bit words to zero in the same launch (a batch plan's).
+int spread_begin(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s,
+                 unsigned *counters = nullptr, int64_t n_counters = 0);
 int spread_scale(const ot_tree *t, const FxWs &ws, int dtype, int mode, const void *force, int64_t n, hipStream_t s);
 int spread_epilogue(const ot_tree *t, const FxWs &ws, int dtype, int mode, int accumulate, void *fout, hipStream_t s);
 FxWs fx_ws(void *work);
