@@ -10,8 +10,10 @@
 // LSD passes, see point_sort_key_bits).
 //
 // A pass takes tiles of 2048 points: the keys are staged in LDS with
-// coalesced loads, ranked stably by the digit with eight 1-bit splits, and
-// every digit's run is written contiguously; the records, read once in
+// coalesced loads, ranked by the digit (stably, with eight 1-bit splits,
+// except in the first pass, whose order no later pass relies on: there each
+// key takes the next slot of its digit from an LDS counter), and every
+// digit's run is written contiguously; the records, read once in
 // input order, move to their sorted slots through LDS in small chunks.  (Tiles of 4096 and 8192
 // points give longer runs but fewer workgroups in flight, and were slower.)  The
 // first pass's digit counts come from the key kernel, and the first pass also
@@ -195,21 +197,22 @@ __global__ __launch_bounds__(kThreads) void k_point_hist(const uint64_t *__restr
     for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + blockIdx.x] = hist[d];
 }
 
-// One stable counting pass over tiles of kTile points.  Records come from
-// rin (R values per point) or, in the first pass, from pos (3 per point) and
-// force (3 per point, R = 6 only).  maxbits != null: also max |F| over the
-// finite force components.
+// One counting pass over tiles of kTile points, stable except the first
+// (first != 0).  Records come from rin (R values per point) or, in the first
+// pass, from pos (3 per point) and force (3 per point, R = 6 only).
+// maxbits != null: also max |F| over the finite force components.
 template <typename T, int R>
 __global__ __launch_bounds__(kThreads) void k_point_scatter(
     const uint64_t *__restrict__ kin, const T *__restrict__ rin, const T *__restrict__ pos,
     const T *__restrict__ force, uint64_t *__restrict__ kout, T *__restrict__ rout, int64_t n, int shift,
-    const uint32_t *__restrict__ offs, int nblocks, unsigned long long *__restrict__ maxbits)
+    const uint32_t *__restrict__ offs, int nblocks, unsigned long long *__restrict__ maxbits, int first)
 {
     __shared__ uint32_t sk[kPadded];
     __shared__ uint16_t si[kPadded];
     __shared__ uint32_t sh_w[kThreads / 64];
     __shared__ uint32_t dstart[kBuckets];
     __shared__ uint32_t dcount[kBuckets];
+    __shared__ uint32_t dcur[kBuckets];
     __shared__ unsigned long long sh_max[kThreads / 64];
 
     // Workgroups go round-robin over the 8 XCDs; each XCD takes a contiguous
@@ -256,7 +259,10 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
             }
         }
     }
-    for (int d = threadIdx.x; d < kBuckets; d += kThreads) dcount[d] = 0;
+    for (int d = threadIdx.x; d < kBuckets; d += kThreads) {
+        dcount[d] = 0;
+        dcur[d] = 0;
+    }
     __syncthreads();
     for (int j = 0; j < kItems; ++j) {
         const int li = j * kThreads + threadIdx.x;
@@ -266,6 +272,29 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         si[pad(li)] = (uint16_t)li;
     }
     __syncthreads();
+    {
+        uint32_t tot;
+        const uint32_t c = dcount[threadIdx.x];
+        dstart[threadIdx.x] = exscan_256(c, sh_w, tot);
+    }
+    __syncthreads();
+    if (first) {
+        // The first pass need not be stable (the later, stable passes keep
+        // its order only inside groups of equal key, where any order will
+        // do): each item takes the next slot of its digit's run from an LDS
+        // counter, instead of eight one-bit split rounds.
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int li = j * kThreads + threadIdx.x;
+            if (li < valid) {
+                const uint32_t d = ((kk[j] & kIdMask) >> shift) & (kBuckets - 1);
+                const uint32_t p = dstart[d] + atomicAdd(&dcur[d], 1u);
+                sk[pad((int)p)] = kk[j];
+                si[pad((int)p)] = (uint16_t)li;
+            }
+        }
+        __syncthreads();
+    } else {
     uint32_t k[kItems];
     uint32_t x[kItems];
     const int t0 = threadIdx.x * kItems;
@@ -300,12 +329,7 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
             __syncthreads();
         }
     }
-    {
-        uint32_t tot;
-        const uint32_t c = dcount[threadIdx.x];
-        dstart[threadIdx.x] = exscan_256(c, sh_w, tot);
     }
-    __syncthreads();
     // Records are read once, in input order (coalesced), into registers and
     // reach their sorted positions through LDS in chunks of CW values (the
     // whole tile's records at once would take too much LDS: fewer
@@ -399,7 +423,7 @@ void sort_passes(const TreeView &tv, int64_t n, int64_t n_leaves, int shift, int
         exclusive_scan(counts, offs, nc, tmp, s);
         hipLaunchKernelGGL((k_point_scatter<T, R>), dim3(nb), dim3(kThreads), 0, s, kin, rin, pos, force, b.kv[o],
                            b.rec[o], n, shift + sh, (const uint32_t *)offs, nb,
-                           sh == 0 ? maxbits : (unsigned long long *)nullptr);
+                           sh == 0 ? maxbits : (unsigned long long *)nullptr, sh == 0 ? 1 : 0);
         kin = b.kv[o];
         rin = b.rec[o];
         cur = o;
