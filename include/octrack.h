@@ -138,7 +138,7 @@ typedef struct {
 } ot_tuning;
 
 /* Sort the points by host leaf before the persistent pass: locate, then
- * stable 8-bit radix passes over the host ids down to groups of at most 64
+ * 8-bit radix passes (all stable but the first) over the host ids down to groups of at most 64
  * consecutive ids (two passes up to 4 M leaves, three above) that carry
  * positions and forces into plan-owned buffers; the pass then visits the
  * points in that order and writes each result at its point's input row.
