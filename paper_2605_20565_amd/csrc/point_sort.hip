@@ -295,40 +295,41 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         }
         __syncthreads();
     } else {
-    uint32_t k[kItems];
-    uint32_t x[kItems];
-    const int t0 = threadIdx.x * kItems;
-#pragma unroll
-    for (int j = 0; j < kItems; ++j) {
-        k[j] = sk[pad(t0 + j)];
-        x[j] = si[pad(t0 + j)];
-    }
-    __syncthreads();
-    for (int b = 0; b < kBits; ++b) {
-        uint32_t zeros = 0;
-#pragma unroll
-        for (int j = 0; j < kItems; ++j) zeros += 1u - (((k[j] & kIdMask) >> (shift + b)) & 1u);
-        uint32_t total_zeros;
-        uint32_t zb = exscan_256(zeros, sh_w, total_zeros);
+        // stable: eight one-bit splits, each a block-wide scan of the zeros
+        uint32_t k[kItems];
+        uint32_t x[kItems];
+        const int t0 = threadIdx.x * kItems;
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
-            const uint32_t bit = ((k[j] & kIdMask) >> (shift + b)) & 1u;
-            const uint32_t g = (uint32_t)(t0 + j);
-            const uint32_t p = bit ? total_zeros + (g - zb) : zb;
-            zb += 1u - bit;
-            sk[pad((int)p)] = k[j];
-            si[pad((int)p)] = (uint16_t)x[j];
+            k[j] = sk[pad(t0 + j)];
+            x[j] = si[pad(t0 + j)];
         }
         __syncthreads();
-        if (b + 1 < kBits) {
+        for (int b = 0; b < kBits; ++b) {
+            uint32_t zeros = 0;
+#pragma unroll
+            for (int j = 0; j < kItems; ++j) zeros += 1u - (((k[j] & kIdMask) >> (shift + b)) & 1u);
+            uint32_t total_zeros;
+            uint32_t zb = exscan_256(zeros, sh_w, total_zeros);
 #pragma unroll
             for (int j = 0; j < kItems; ++j) {
-                k[j] = sk[pad(t0 + j)];
-                x[j] = si[pad(t0 + j)];
+                const uint32_t bit = ((k[j] & kIdMask) >> (shift + b)) & 1u;
+                const uint32_t g = (uint32_t)(t0 + j);
+                const uint32_t p = bit ? total_zeros + (g - zb) : zb;
+                zb += 1u - bit;
+                sk[pad((int)p)] = k[j];
+                si[pad((int)p)] = (uint16_t)x[j];
             }
             __syncthreads();
+            if (b + 1 < kBits) {
+#pragma unroll
+                for (int j = 0; j < kItems; ++j) {
+                    k[j] = sk[pad(t0 + j)];
+                    x[j] = si[pad(t0 + j)];
+                }
+                __syncthreads();
+            }
         }
-    }
     }
     // Records are read once, in input order (coalesced), into registers and
     // reach their sorted positions through LDS in chunks of CW values (the
