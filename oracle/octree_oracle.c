@@ -347,7 +347,7 @@ static int build_stencil(const orc_tree *t, const double x[3], stencil *st, int 
 /* ---------------------------------------------------------------------------
  * Interpolation (Sec. 2.2):  U_k = sum_n W(x_n - X_k) (dx)^3 u(x_n).
  * field: (n_leaves, 3) in Morton order.  U: (n, 3).  scale (nullable):
- * sum_n |w_n| |u_n,c|, the magnitude against which rounding is judged.
+ * sum_n |w_n| |u_n,c|, the magnitude that bounds the rounding error.
  * Points without a host cell get U = 0.
  * ------------------------------------------------------------------------- */
 void orc_interpolate(const orc_tree *t, const double *field, const double *pos, int64_t n,
