@@ -254,23 +254,25 @@ struct LdsSink {
         }
     }
 
-    // All threads of the workgroup; leaves the table empty.
+    // All threads of the workgroup; leaves the table empty.  Value e of the
+    // table (slot e / 3, component e % 3) goes to lane e of the sweep, so the
+    // three components of a slot are added by neighbouring lanes of one
+    // instruction: a run of neighbouring leaves becomes one contiguous span
+    // of device memory per instruction, not three strided ones.  The keys
+    // are cleared after a barrier, once every lane has read its slot's key.
     __device__ __forceinline__ void flush()
     {
         __syncthreads();
-        for (int i = threadIdx.x; i < S; i += blockDim.x) {
+        for (int e = threadIdx.x; e < kVals; e += blockDim.x) {
+            const uint32_t i = (uint32_t)e / 3u;
             const uint32_t key = keys[i];
             if (key) {
-                const int64_t j = 3 * (int64_t)(key - 1u);
-                global_add<T, MODE>(fout, facc, j, vals[3 * i]);
-                global_add<T, MODE>(fout, facc, j + 1, vals[3 * i + 1]);
-                global_add<T, MODE>(fout, facc, j + 2, vals[3 * i + 2]);
-                keys[i] = 0u;
-                vals[3 * i] = Acc(0);
-                vals[3 * i + 1] = Acc(0);
-                vals[3 * i + 2] = Acc(0);
+                global_add<T, MODE>(fout, facc, 3 * (int64_t)(key - 1u) + (int64_t)(e - 3 * (int)i), vals[e]);
+                vals[e] = Acc(0);
             }
         }
+        __syncthreads();
+        for (int i = threadIdx.x; i < S; i += blockDim.x) keys[i] = 0u;
         __syncthreads();
     }
 };
