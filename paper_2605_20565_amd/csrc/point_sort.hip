@@ -189,10 +189,16 @@ __global__ __launch_bounds__(kThreads) void k_point_hist(const uint64_t *__restr
     for (int i = threadIdx.x; i < kBuckets; i += kThreads) hist[i] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
-    for (int j = threadIdx.x; j < kTile; j += kThreads) {
-        const int64_t i = base + j;
-        if (i < n) atomicAdd(&hist[(((uint32_t)(kv[i] >> 32) & kIdMask) >> shift) & (kBuckets - 1)], 1u);
+    // all of a thread's words loaded (clamped indices) before any is counted
+    uint32_t hk[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const int64_t i = base + j * kThreads + threadIdx.x;
+        hk[j] = (uint32_t)(kv[i < n ? i : base] >> 32);
     }
+#pragma unroll
+    for (int j = 0; j < kItems; ++j)
+        if (base + j * kThreads + threadIdx.x < n) atomicAdd(&hist[((hk[j] & kIdMask) >> shift) & (kBuckets - 1)], 1u);
     __syncthreads();
     for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + blockIdx.x] = hist[d];
 }
@@ -225,37 +231,46 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     const int valid = rem < kTile ? (int)rem : kTile;
     // The tile's words and records, read once in input order (coalesced) and
     // before the ranking, so that their latency overlaps it.
+    // Every item loads at a clamped index (the tile's first point stands in
+    // for the padding), with no branch around the loads: a load inside a
+    // branch is waited for where the branch joins, which had put the eight
+    // items' round trips one after another.
     T rv[kItems][R];
     uint32_t lo[kItems], kk[kItems];
+    uint64_t wv[kItems];
+    if (rin) {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int li = j * kThreads + threadIdx.x;
+            const int64_t src = base + (li < valid ? li : 0);
+            wv[j] = kin[src];
+#pragma unroll
+            for (int c = 0; c < R; ++c) rv[j][c] = rin[R * src + c];
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int li = j * kThreads + threadIdx.x;
+            const int64_t src = base + (li < valid ? li : 0);
+            wv[j] = kin[src];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) rv[j][c] = pos[3 * src + c];
+#pragma unroll
+            for (int c = 3; c < R; ++c) rv[j][c] = force[3 * src + (c - 3)];
+        }
+    }
     unsigned long long mx = 0;
     bool bad = false;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        const int li = j * kThreads + threadIdx.x;
-        lo[j] = 0u;
-        kk[j] = 0xFFFFFFFFu;   // padding sorts last
+        const bool in = j * kThreads + (int)threadIdx.x < valid;
+        kk[j] = in ? (uint32_t)(wv[j] >> 32) : 0xFFFFFFFFu;   // padding sorts last
+        lo[j] = in ? (uint32_t)wv[j] : 0u;
+        if (maxbits && in) {
 #pragma unroll
-        for (int c = 0; c < R; ++c) rv[j][c] = T(0);
-        if (li < valid) {
-            const int64_t src = base + li;
-            const uint64_t w = kin[src];
-            kk[j] = (uint32_t)(w >> 32);
-            lo[j] = (uint32_t)w;
-            if (rin) {
-#pragma unroll
-                for (int c = 0; c < R; ++c) rv[j][c] = rin[R * src + c];
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) rv[j][c] = pos[3 * src + c];
-#pragma unroll
-                for (int c = 3; c < R; ++c) rv[j][c] = force[3 * src + (c - 3)];
-            }
-            if (maxbits) {
-#pragma unroll
-                for (int c = 3; c < R; ++c) {
-                    if (isfinite(rv[j][c])) mx = std::max(mx, abs_bits_of(rv[j][c]));
-                    else bad = true;
-                }
+            for (int c = 3; c < R; ++c) {
+                if (isfinite(rv[j][c])) mx = std::max(mx, abs_bits_of(rv[j][c]));
+                else bad = true;
             }
         }
     }
@@ -351,17 +366,16 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     // sorted position i = j * kThreads + thread: its destination and source slot
     int64_t dstv[kItems];
     int srcv[kItems];
+    // (no branch around the offset loads either: the padding's keys, sorted
+    // last, also name a digit, so their loads stay in bounds)
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int i = j * kThreads + threadIdx.x;
-        dstv[j] = -1;
-        srcv[j] = 0;
-        if (i < valid) {
-            const uint32_t key = sk[pad(i)];
-            const uint32_t d = ((key & kIdMask) >> shift) & (kBuckets - 1);
-            dstv[j] = (int64_t)offs[(int64_t)d * nblocks + tile] + (i - (int)dstart[d]);
-            srcv[j] = si[pad(i)];
-        }
+        const uint32_t key = sk[pad(i)];
+        const uint32_t d = ((key & kIdMask) >> shift) & (kBuckets - 1);
+        const int64_t o = (int64_t)offs[(int64_t)d * nblocks + tile];
+        dstv[j] = i < valid ? o + (i - (int)dstart[d]) : -1;
+        srcv[j] = i < valid ? (int)si[pad(i)] : 0;
     }
 #pragma unroll
     for (int ch = 0; ch < kChunks; ++ch) {
@@ -380,21 +394,25 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kItems; ++j) {
-            if (dstv[j] < 0) continue;
+            // LDS reads outside the branch, stores inside it
             const int i = j * kThreads + threadIdx.x;
+            const Chunk c = stg[pad(srcv[j])];
+            const uint32_t key = sk[pad(i)];
             if constexpr (kF6) {
+                if (dstv[j] < 0) continue;
                 // a record starts at 24 dst bytes: 8-byte aligned
-                const float4 c = stg[pad(srcv[j])];
                 float *dst = reinterpret_cast<float *>(rout) + 6 * dstv[j];
                 if (ch == 0) {
                     *reinterpret_cast<F4u *>(dst) = F4u{c.x, c.y, c.z, c.w};
                 } else {
                     *reinterpret_cast<float2 *>(dst + 4) = make_float2(c.x, c.y);
-                    kout[dstv[j]] = ((uint64_t)sk[pad(i)] << 32) | __float_as_uint(c.z);
+                    kout[dstv[j]] = ((uint64_t)key << 32) | __float_as_uint(c.z);
                 }
             } else {
-                if (ch == 0) kout[dstv[j]] = ((uint64_t)sk[pad(i)] << 32) | slo[pad(srcv[j])];
-                reinterpret_cast<Chunk *>(rout)[(R * dstv[j]) / CW + ch] = stg[pad(srcv[j])];
+                const uint32_t lw = ch == 0 ? slo[pad(srcv[j])] : 0u;
+                if (dstv[j] < 0) continue;
+                if (ch == 0) kout[dstv[j]] = ((uint64_t)key << 32) | lw;
+                reinterpret_cast<Chunk *>(rout)[(R * dstv[j]) / CW + ch] = c;
             }
         }
         __syncthreads();
