@@ -390,24 +390,39 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
                     v[d] = force[kp + d];
                 }
             }
+            // the gathers of one z-plane of the stencil (nine rows) are issued
+            // together before any is used (the scheduler had kept about six in
+            // flight); a node dropped at a wall has entry 0 and loads row 0
 #pragma unroll
-            for (int q = 0; q < 27; ++q) {
-                const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
-                const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
-                if (!PER && (st.valid & need) != need) continue;
-                const int64_t j = 3 * (int64_t)(ent[q] & kIdMask);
-                const T f0 = field[j], f1 = field[j + 1], f2 = field[j + 2];
-                if (OPS & kOpInterp) {
-                    const T w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
-                    U[0] = fma(w, f0, U[0]);
-                    U[1] = fma(w, f1, U[1]);
-                    U[2] = fma(w, f2, U[2]);
+            for (int oz = 0; oz < 3; ++oz) {
+                T fr[9][3];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int64_t j = 3 * (int64_t)(ent[9 * oz + i] & kIdMask);
+                    fr[i][0] = field[j];
+                    fr[i][1] = field[j + 1];
+                    fr[i][2] = field[j + 2];
                 }
-                if (OPS & kOpGrad) {
-                    const T dot = fma(v[0], f0, fma(v[1], f1, v[2] * f2));
-                    G[0] = fma(dot * dw[0][ox], st.w[1][oy] * st.w[2][oz], G[0]);
-                    G[1] = fma(dot * st.w[0][ox], dw[1][oy] * st.w[2][oz], G[1]);
-                    G[2] = fma(dot * st.w[0][ox], st.w[1][oy] * dw[2][oz], G[2]);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int q = 9 * oz + i;
+                    const int ox = q % 3, oy = (q / 3) % 3;
+                    const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
+                    if (!PER && (st.valid & need) != need) continue;
+                    const T f0 = fr[i][0], f1 = fr[i][1], f2 = fr[i][2];
+                    if (OPS & kOpInterp) {
+                        const T w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
+                        U[0] = fma(w, f0, U[0]);
+                        U[1] = fma(w, f1, U[1]);
+                        U[2] = fma(w, f2, U[2]);
+                    }
+                    if (OPS & kOpGrad) {
+                        const T dot = fma(v[0], f0, fma(v[1], f1, v[2] * f2));
+                        G[0] = fma(dot * dw[0][ox], st.w[1][oy] * st.w[2][oz], G[0]);
+                        G[1] = fma(dot * st.w[0][ox], dw[1][oy] * st.w[2][oz], G[1]);
+                        G[2] = fma(dot * st.w[0][ox], st.w[1][oy] * dw[2][oz], G[2]);
+                    }
                 }
             }
         }
