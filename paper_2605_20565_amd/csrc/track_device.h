@@ -301,7 +301,7 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
                                                const T (&X)[3], int rs, const T *__restrict__ field,
                                                const T *__restrict__ force, int32_t *__restrict__ ids,
                                                T *__restrict__ vel, Sink &sink, T *__restrict__ grad,
-                                               const int32_t *__restrict__ hid)
+                                               const int32_t *__restrict__ hid, const T *Fpre = nullptr)
 {
     const int64_t kd = sorted ? (int64_t)(uint32_t)word : k;
     const int64_t kp = (int64_t)rs * k;
@@ -387,7 +387,7 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
                     delta3_grad<T>(t, r, wtmp, dw[d]);
 #pragma unroll
                     for (int o = 0; o < 3; ++o) dw[d][o] *= sc;
-                    v[d] = force[kp + d];
+                    v[d] = Fpre ? Fpre[d] : force[kp + d];
                 }
             }
             // the gathers of one z-plane of the stencil (nine rows) are issued
@@ -433,7 +433,8 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
             // 27 gathered values alive through it
             if (OPS & kOpInterp) asm volatile("" : "+v"(U[0]), "+v"(U[1]), "+v"(U[2]));
             if (OPS & kOpGrad) asm volatile("" : "+v"(G[0]), "+v"(G[1]), "+v"(G[2]));
-            const T F[3] = {force[kp], force[kp + 1], force[kp + 2]};
+            const T F[3] = {Fpre ? Fpre[0] : force[kp], Fpre ? Fpre[1] : force[kp + 1],
+                            Fpre ? Fpre[2] : force[kp + 2]};
             uint32_t live = (1u << 27) - 1u;
             if (!PER) {
 #pragma unroll
@@ -574,12 +575,19 @@ __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, i
             track_point<T, OPS, PER, Sink>(tv, k, kv, rs, pos, field, force, ids, vel, sink, grad, hid);
         return;
     }
-    // sorted records: the next point's word and position are loaded before
-    // this point's work, so they arrive while it runs
+    // sorted records: the next point's word, position and force are loaded
+    // before this point's work, so they arrive while it runs
+    constexpr bool kF = (OPS & (kOpSpread | kOpGrad)) != 0;
     int64_t k = start + threadIdx.x;
     if (k >= end) return;
     uint64_t w = kv[k];
     T X[3] = {pos[(int64_t)rs * k], pos[(int64_t)rs * k + 1], pos[(int64_t)rs * k + 2]};
+    T F[3] = {T(0), T(0), T(0)};
+    if (kF) {
+        F[0] = force[(int64_t)rs * k];
+        F[1] = force[(int64_t)rs * k + 1];
+        F[2] = force[(int64_t)rs * k + 2];
+    }
     for (;;) {
         const int64_t kn = k + blockDim.x;
         const bool more = kn < end;
@@ -588,17 +596,28 @@ __device__ __forceinline__ void track_range(const TreeView &tv, int64_t start, i
         // made the prefetch wait before the current point's work
         const int64_t kc = more ? kn : k;
         const uint64_t wn = kv[kc];
-        T Xn[3];
+        T Xn[3], Fn[3];
         Xn[0] = pos[(int64_t)rs * kc];
         Xn[1] = pos[(int64_t)rs * kc + 1];
         Xn[2] = pos[(int64_t)rs * kc + 2];
-        track_point_at<T, OPS, PER, Sink>(tv, k, true, w, X, rs, field, force, ids, vel, sink, grad, nullptr);
+        if (kF) {
+            Fn[0] = force[(int64_t)rs * kc];
+            Fn[1] = force[(int64_t)rs * kc + 1];
+            Fn[2] = force[(int64_t)rs * kc + 2];
+        }
+        track_point_at<T, OPS, PER, Sink>(tv, k, true, w, X, rs, field, force, ids, vel, sink, grad, nullptr,
+                                          kF ? F : nullptr);
         if (!more) break;
         k = kn;
         w = wn;
         X[0] = Xn[0];
         X[1] = Xn[1];
         X[2] = Xn[2];
+        if (kF) {
+            F[0] = Fn[0];
+            F[1] = Fn[1];
+            F[2] = Fn[2];
+        }
     }
 }
 
