@@ -60,6 +60,17 @@ struct __attribute__((aligned(4))) F4u {
     float x, y, z, w;
 };
 
+// Tile of workgroup blockIdx.x.  Workgroups go round-robin over the 8 XCDs;
+// each XCD takes a contiguous range of tiles, so that what neighbouring
+// tiles write next to each other (the digit counts of one digit, the ends of
+// one digit's runs) meets in the same L2 instead of in partial lines of up
+// to eight.
+__device__ __forceinline__ int xcd_tile(int nblocks)
+{
+    const int xg = (int)(blockIdx.x & 7u), xk = (int)(blockIdx.x >> 3), xq = nblocks >> 3, xr = nblocks & 7;
+    return xg * xq + (xg < xr ? xg : xr) + xk;
+}
+
 // LDS index with one pad word per 32: the blocked reads (stride kItems) and
 // the striped writes both spread over the banks.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 5); }
@@ -126,7 +137,8 @@ __global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n,
     __shared__ uint32_t hist[kBuckets];
     for (int i = threadIdx.x; i < kBuckets; i += kThreads) hist[i] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int tile = xcd_tile(nblocks);
+    const int64_t base = (int64_t)tile * kTile;
     uint32_t I[kItems][3];
     uint32_t e[kItems];
     bool ok[kItems];
@@ -179,7 +191,7 @@ __global__ __launch_bounds__(kThreads) void k_point_keys(TreeView tv, int64_t n,
         }
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + blockIdx.x] = hist[d];
+    for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + tile] = hist[d];
 }
 
 __global__ __launch_bounds__(kThreads) void k_point_hist(const uint64_t *__restrict__ kv, int64_t n, int shift,
@@ -188,7 +200,8 @@ __global__ __launch_bounds__(kThreads) void k_point_hist(const uint64_t *__restr
     __shared__ uint32_t hist[kBuckets];
     for (int i = threadIdx.x; i < kBuckets; i += kThreads) hist[i] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int tile = xcd_tile(nblocks);
+    const int64_t base = (int64_t)tile * kTile;
     // all of a thread's words loaded (clamped indices) before any is counted
     uint32_t hk[kItems];
 #pragma unroll
@@ -200,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_point_hist(const uint64_t *__restr
     for (int j = 0; j < kItems; ++j)
         if (base + j * kThreads + threadIdx.x < n) atomicAdd(&hist[((hk[j] & kIdMask) >> shift) & (kBuckets - 1)], 1u);
     __syncthreads();
-    for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + blockIdx.x] = hist[d];
+    for (int d = threadIdx.x; d < kBuckets; d += kThreads) counts[(int64_t)d * nblocks + tile] = hist[d];
 }
 
 // One counting pass over tiles of kTile points, stable except the first
@@ -221,11 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
     __shared__ uint32_t dcur[kBuckets];
     __shared__ unsigned long long sh_max[kThreads / 64];
 
-    // Workgroups go round-robin over the 8 XCDs; each XCD takes a contiguous
-    // range of tiles, so the ends of neighbouring tiles' digit runs (partial
-    // cache lines) meet in the same L2.
-    const int xg = (int)(blockIdx.x & 7u), xk = (int)(blockIdx.x >> 3), xq = nblocks >> 3, xr = nblocks & 7;
-    const int tile = xg * xq + (xg < xr ? xg : xr) + xk;
+    const int tile = xcd_tile(nblocks);
     const int64_t base = (int64_t)tile * kTile;
     const int64_t rem = n - base;
     const int valid = rem < kTile ? (int)rem : kTile;
