@@ -4,7 +4,8 @@
 One step = host-cell search + interpolation + spreading of every point of the
 workload (8 bubbles' markers and 10^7 uniform particles on a band-refined
 l 7->10 octree, FP32, fixed-point spreading) in one batched persistent pass
-replayed from a HIP graph.  Inputs are resident in HBM before timing starts.
+(with the in-step sort: 14 kernels on one stream).  Inputs are resident in
+HBM before timing starts.
 
 Prints one JSON line: points/s, the dominant kernel's achieved bandwidth
 against the HBM peak (roofline), the FP64 oracle timed on a bounded sample on
@@ -201,7 +202,7 @@ def main():
     def step():
         plan.run(pos, field=field, force=force, ids=ids, vel=vel, field_out=fout)
 
-    # ---- timed region: K graph replays back to back -------------------------
+    # ---- timed region: K steps back to back ----------------------------------
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -214,7 +215,7 @@ def main():
     value = n * args.steps / elapsed
     log(f"[bench] {ms_per_step:.3f} ms/step, {value:.4g} points/s")
 
-    # ---- dominant kernel duration: HIP events around it inside the graph ----
+    # ---- dominant kernel duration: HIP events around it on its stream -------
     plan.set_timing(True)
     step()
     torch.cuda.synchronize()
@@ -260,8 +261,8 @@ def main():
         "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {**workload_desc(w, args.config), "precision": args.dtype, "spread_mode": args.mode,
                    "point_order": "host-leaf order (pre-sorted)" if args.presorted else "random (as generated)",
-                   "path": "batched persistent kernel, HIP graph" + (", in-step sort of points by host leaf"
-                                                                      if shape["sort_points"] else ""),
+                   "path": "batched persistent kernel" + (", in-step sort of points by host leaf"
+                                                          if shape["sort_points"] else ""),
                    "block": shape["block"] or "library default", "tile": shape["tile"] or "library default",
                    "tiles": n_tiles, "workgroups": grid, "autotuned": not args.no_tune,
                    "host_major_windows": hm_windows, "windows_to_per_point_pass": hm_handed},
@@ -419,7 +420,7 @@ def _workload_on_gpu(w, dev, dt, ot, torch):
 
 def workload3_measure(args, dev, ot, torch, timeit):
     """Workload 3 (256 bubbles of log-uniform size + 64 particle groups, 320
-    uneven instances): one batched, sorted, graph-replayed pass against one
+    uneven instances): one batched, sorted pass against one
     plain fused launch per instance, FP32 FIXED."""
     import synth
     t0 = time.time()
@@ -453,7 +454,7 @@ def workload3_measure(args, dev, ot, torch, timeit):
            "per_instance_launches_ms_per_step": round(ms_i, 4), "batched_speedup": round(ms_i / ms_b, 2),
            "batched_shape": best.label(),
            "touched_leaves": touched, "batched_roofline": _roof(n, touched, ms_b, "f32"),
-           "path": "batched persistent kernel, HIP graph, in-step sort; FP32, FIXED"}
+           "path": "batched persistent kernel, in-step sort; FP32, FIXED"}
     tree.close()
     return out
 
@@ -706,8 +707,11 @@ def config1_latency(dev, dt, mode, ot, torch, timeit):
     pl = ot.BatchPlan(t1, offs, [7] * (len(offs) - 1), dtype=dt, mode=mode)
     batched = timeit(lambda: pl.run(P, field=U, force=F, ids=ids, vel=vel, field_out=fo), 50)
     pl.close()
+    pg = ot.BatchPlan(t1, offs, [7] * (len(offs) - 1), dtype=dt, mode=mode, graph=True)
+    graph = timeit(lambda: pg.run(P, field=U, force=F, ids=ids, vel=vel, field_out=fo), 50)
+    pg.close()
     return {"points": n, "leaves": t1.n_leaves, "plain_fused_launch": round(plain * 1e3, 1),
-            "batched_graph": round(batched * 1e3, 1)}
+            "batched": round(batched * 1e3, 1), "batched_graph_replay": round(graph * 1e3, 1)}
 
 
 def oracle_check(w, tree, dev, dt, torch, n_sample=20000):

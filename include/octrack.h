@@ -156,6 +156,12 @@ typedef struct {
  * per-point pass.  Needs OT_TUNE_SORT_POINTS. */
 #define OT_TUNE_HOST_MAJOR 2
 
+/* Replay the plan's kernels through a captured HIP graph: one graph launch
+ * per run instead of the plan's 4 to 14 kernel launches, which saves host
+ * time per run.  Off by default: on this GPU the graph launch made a run
+ * about 7 us longer on 11 k points and no faster on 10^7. */
+#define OT_TUNE_GRAPH 4
+
 /* Morton keys of leaf anchors (Sec. 3.1: leaves are ordered along the
  * Z-curve).  anchors: (n, 3) uint32, each < 2^l_max.  keys: (n,) uint64.
  * Errors: OT_ERR_INVALID (null with n > 0, n < 0), OT_ERR_LEVEL_RANGE
@@ -424,7 +430,8 @@ int ot_mdf(const ot_tree *tree, void *field, const void *pos, const void *target
            void *force_eul, void *work, void *stream);
 
 /* Batched pass over many point sets of uneven size (bubbles' markers and
- * particle groups) in one persistent launch captured in a HIP graph.
+ * particle groups) in one persistent launch (with OT_TUNE_GRAPH, the
+ * plan's launches replay as one HIP graph).
  * offsets: host (n_inst + 1,) int64, ascending, offsets[0] = 0; instance i
  * owns points [offsets[i], offsets[i+1]).  ops: host (n_inst,) OT_OP_* bits
  * per instance.  Tiles of <= tuning.tile points never straddle instances.
@@ -438,8 +445,9 @@ int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets, const int3
                          ot_batch_plan **out);
 
 /* Run a plan: like ot_track over all instances (field_out overwritten).
- * The first run with a given set of pointers and stream captures a graph;
- * later runs with the same set replay it. */
+ * The plan's kernels are enqueued on the stream.  With OT_TUNE_GRAPH the
+ * first run with a given set of pointers captures them in a graph, and
+ * later runs with the same set replay it on the stream. */
 int ot_batch_run(ot_batch_plan *plan, const void *field, const void *force, const void *pos,
                  int32_t *ids, void *vel, void *field_out, void *stream);
 
@@ -458,7 +466,7 @@ int ot_batch_run_grad(ot_batch_plan *plan, const void *field, const void *force,
  * recorded just before and after the persistent kernel;
  * ot_batch_last_kernel_ms returns the kernel's duration in the last
  * completed run (OT_ERR_HIP while it is still in flight).  enable = 0 returns
- * to graph replays. */
+ * to the plan's usual launches (graph replays for OT_TUNE_GRAPH plans). */
 int ot_batch_plan_timing(ot_batch_plan *plan, int32_t enable);
 int ot_batch_last_kernel_ms(const ot_batch_plan *plan, float *ms);
 

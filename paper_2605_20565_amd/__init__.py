@@ -58,6 +58,7 @@ class Tuning(ctypes.Structure):
 
 OT_TUNE_SORT_POINTS = 1
 OT_TUNE_HOST_MAJOR = 2
+OT_TUNE_GRAPH = 4
 
 
 EXPORTS = ("ot_encode_keys", "ot_build_tree", "ot_destroy_tree", "ot_tree_info_get", "ot_tree_leaves",
@@ -549,15 +550,16 @@ def body_sums(vec: torch.Tensor, pos: torch.Tensor, offsets, centres: torch.Tens
 
 
 class BatchPlan:
-    """Many point sets in one persistent, graph-replayed pass (``ot_batch_*``)."""
+    """Many point sets in one persistent pass (``ot_batch_*``); with ``graph`` its launches replay as one
+    captured HIP graph."""
 
     def __init__(self, tree: Tree, offsets: Sequence[int], ops: Sequence[int], dtype=torch.float32,
                  mode="atomic", block: int = 0, tile: int = 0, grid: int = 0, sort_points: bool = False,
-                 host_major: bool = False):
+                 host_major: bool = False, graph: bool = False):
         off = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
         opa = (ctypes.c_int32 * len(ops))(*[int(v) for v in ops])
         tun = Tuning(block, tile, grid, (OT_TUNE_SORT_POINTS if sort_points else 0) |
-                     (OT_TUNE_HOST_MAJOR if host_major else 0))
+                     (OT_TUNE_HOST_MAJOR if host_major else 0) | (OT_TUNE_GRAPH if graph else 0))
         h = ctypes.c_void_p()
         code = OT_F32 if dtype == torch.float32 else OT_F64
         _check(lib.ot_batch_plan_create(tree.handle, off, opa, len(ops), code, _mode_code(mode), ctypes.byref(tun),

@@ -145,6 +145,7 @@ extern "C" int ot_batch_plan_create(const ot_tree *tree, const int64_t *offsets,
     p->n_points = offsets[n_inst];
     p->n_tiles = (int64_t)starts.size();
     p->have_graph = false;
+    p->use_graph = tuning && (tuning->flags & OT_TUNE_GRAPH);
     p->sort_points = sort_points;
     p->ops_all = ops_all;
     p->grad_plan = (ops_union & kOpGrad) != 0;
@@ -251,9 +252,10 @@ int run_plan(ot_batch_plan *p, const void *field, const void *force, const void 
     if ((u & kOpSpread) && (!force || !field_out)) return fail(OT_ERR_INVALID, "force or field_out is NULL");
     if ((u & kOpGrad) && (!field || !force || !grad)) return fail(OT_ERR_INVALID, "field, force or grad is NULL");
     hipStream_t s = (hipStream_t)stream;
-    if (p->timing) {
-        // Events recorded inside a captured graph cannot be timed, so a timed
-        // run enqueues the same sequence directly on the caller's stream.
+    if (p->timing || !p->use_graph) {
+        // Plans enqueue their kernels on the caller's stream unless they were
+        // made with OT_TUNE_GRAPH; events recorded inside a captured graph
+        // cannot be timed, so a timed run does the same.
         return enqueue_any(p, field, force, pos, ids, vel, field_out, grad, s);
     }
     const void *key[7] = {field, force, pos, ids, vel, field_out, grad};

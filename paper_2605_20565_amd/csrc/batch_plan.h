@@ -18,6 +18,7 @@ struct ot_batch_plan {
     uint32_t *tile_info;      // device: count | ops << 24
     unsigned *counter;        // device
     hipStream_t capture_stream;
+    bool use_graph;           // OT_TUNE_GRAPH: runs replay a captured graph
     bool have_graph;
     hipGraph_t graph;
     hipGraphExec_t exec;

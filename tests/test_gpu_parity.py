@@ -505,7 +505,7 @@ def test_batch_graph_replays_are_identical(ot, cfg1, cfg1_gpu):
     pts, frc, fld = _inputs(w, o, torch.float32, extra=False)
     P, F, Fd = to_dev(pts, torch.float32), to_dev(frc, torch.float32), to_dev(fld, torch.float32)
     n = P.shape[0]
-    plan = ot.BatchPlan(cfg1_gpu, [0, 1000, n], [7, 7], dtype=torch.float32, mode="fixed")
+    plan = ot.BatchPlan(cfg1_gpu, [0, 1000, n], [7, 7], dtype=torch.float32, mode="fixed", graph=True)
     ids = torch.empty(n, dtype=torch.int32, device="cuda")
     vel = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     fo = torch.empty((cfg1_gpu.n_leaves, 3), dtype=torch.float32, device="cuda")
@@ -524,6 +524,15 @@ def test_batch_graph_replays_are_identical(ot, cfg1, cfg1_gpu):
         torch.cuda.synchronize()
         assert torch.equal(ids, ref[0]) and torch.equal(vel, ref[1]) and torch.equal(fo, ref[2])
     plan.close()
+    # the same plan without the graph: its launches enqueued directly
+    direct = ot.BatchPlan(cfg1_gpu, [0, 1000, n], [7, 7], dtype=torch.float32, mode="fixed")
+    ids.fill_(-1)
+    vel.zero_()
+    fo.fill_(123.0)
+    direct.run(P, field=Fd, force=F, ids=ids, vel=vel, field_out=fo)
+    torch.cuda.synchronize()
+    assert torch.equal(ids, ref[0]) and torch.equal(vel, ref[1]) and torch.equal(fo, ref[2])
+    direct.close()
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
