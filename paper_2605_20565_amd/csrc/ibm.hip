@@ -36,7 +36,8 @@ struct StencilSink {
     int32_t *leaf;   // the point's kNodes entries
     T *wt;           // the point's kNodes entries
     uint32_t *flags;
-    __device__ __forceinline__ void add27(const uint32_t (&ent)[27], uint32_t live, const T (&w)[3][3], const T *)
+    __device__ __forceinline__ void add27(const uint32_t (&ent)[27], uint32_t live, const T (&w)[3][3], const T *,
+                                          const uint32_t (&)[3][3], int)
     {
 #pragma unroll
         for (int q = 0; q < kNodes; ++q) {

@@ -145,7 +145,8 @@ struct DirectSink {
     }
 
     // All 27 stencil nodes of one point; bit q of live: node q exists.
-    __device__ __forceinline__ void add27(const uint32_t (&ent)[27], uint32_t live, const T (&w)[3][3], const T F[3])
+    __device__ __forceinline__ void add27(const uint32_t (&ent)[27], uint32_t live, const T (&w)[3][3], const T F[3],
+                                          const uint32_t (&)[3][3], int)
     {
 #pragma unroll
         for (int q = 0; q < 27; ++q)
@@ -156,10 +157,11 @@ struct DirectSink {
 // Workgroup-local aggregation: an open-addressing table in LDS keyed by leaf
 // id accumulates the contributions of all points the workgroup handles;
 // flush() adds each occupied slot to device memory once.  The first probe is
-// slot = id mod S, so the flush's atomics come in runs of neighbouring
-// addresses; on a collision the probe moves by an odd stride hashed from the
-// id (double hashing), because a workgroup's ids come in runs of consecutive
-// Morton ranks that would otherwise pile up into long occupied clusters.  A
+// the primary slot (primary(): a root-level leaf's Morton index mod S, else
+// id mod S), so the flush's atomics come in runs of neighbouring addresses;
+// on a collision the probe moves by an odd stride hashed from the id (double
+// hashing), because a workgroup's ids come in runs of consecutive Morton
+// ranks that would otherwise pile up into long occupied clusters.  A
 // contribution that finds no slot within kProbe steps goes straight to
 // device memory.  In FIXED mode every value is the same rounded integer
 // either way, so the result does not depend on the path.
@@ -184,13 +186,25 @@ struct LdsSink {
         }
     }
 
+    // Primary slot of a node leaf (entry e = level << 26 | id).  A leaf at
+    // the root table's level is a root cell, and its Morton index there
+    // (root: the index its root lookup used) mod S gives all root cells of a
+    // 16 x 16 x 8 box distinct slots; other leaves take id mod S.  Ids are
+    // ranks, shifted by every refined cell before them in Morton order, so
+    // the ids of one tile's runs of root-level leaves can meet mod S where
+    // their Morton indices do not.  Within a run of root-level leaves both
+    // give neighbouring leaves neighbouring slots.
+    static __device__ __forceinline__ uint32_t primary(uint32_t e, uint32_t root, int lev0)
+    {
+        return (((e >> kLevelShift) & 31u) == (uint32_t)lev0 ? root : e) & (S - 1);
+    }
+
     // Slots after the primary one (double hashing); device memory when none
     // is free within kProbe steps.
-    __device__ __forceinline__ void add_probing(uint32_t leaf, Acc a0, Acc a1, Acc a2)
+    __device__ __forceinline__ void add_probing(uint32_t leaf, uint32_t slot, Acc a0, Acc a1, Acc a2)
     {
         const uint32_t key = leaf + 1u;
         const uint32_t step = ((leaf * 0x9E3779B1u) >> 16) | 1u;
-        uint32_t slot = leaf & (S - 1);
         bool found = false;
 #pragma unroll 1
         for (int p = 1; p < kProbe; ++p) {
@@ -217,21 +231,24 @@ struct LdsSink {
         }
     }
 
-    // All 27 stencil nodes of one point; bit q of live: node q exists.  Every
-    // node first claims or finds its primary slot with one compare-and-swap
-    // (0 -> key; a slot holding the key is left as it is); the 27 swaps are
-    // independent, so they are in flight together instead of a chain of LDS
-    // round trips per node.  Keys are only removed by flush(), after a
-    // barrier, so a slot that reads as this key stays this key's.  A node
-    // whose primary slot holds another key probes further.
-    __device__ __forceinline__ void add27(const uint32_t (&ent)[27], uint32_t live, const T (&w)[3][3], const T F[3])
+    // All 27 stencil nodes of one point; bit q of live: node q exists; R:
+    // the stencil's spread root-level digits, lev0 the root table's level.
+    // Every node first claims or finds its primary slot with one
+    // compare-and-swap (0 -> key; a slot holding the key is left as it is);
+    // the 27 swaps are independent, so they are in flight together instead
+    // of a chain of LDS round trips per node.  Keys are only removed by
+    // flush(), after a barrier, so a slot that reads as this key stays this
+    // key's.  A node whose primary slot holds another key probes further.
+    __device__ __forceinline__ void add27(const uint32_t (&ent)[27], uint32_t live, const T (&w)[3][3], const T F[3],
+                                          const uint32_t (&R)[3][3], int lev0)
     {
         uint32_t hit = 0u;
 #pragma unroll
         for (int q = 0; q < 27; ++q) {
             if ((live >> q) & 1u) {
                 const uint32_t leaf = ent[q] & kIdMask;
-                const uint32_t old = atomicCAS(&keys[leaf & (S - 1)], 0u, leaf + 1u);
+                const uint32_t slot = primary(ent[q], R[0][q % 3] | (R[1][(q / 3) % 3] << 1) | (R[2][q / 9] << 2), lev0);
+                const uint32_t old = atomicCAS(&keys[slot], 0u, leaf + 1u);
                 hit |= (uint32_t)(old == 0u || old == leaf + 1u) << q;
             }
         }
@@ -243,13 +260,13 @@ struct LdsSink {
             const Acc a0 = to_acc<T, MODE>(wq, F[0], scale);
             const Acc a1 = to_acc<T, MODE>(wq, F[1], scale);
             const Acc a2 = to_acc<T, MODE>(wq, F[2], scale);
+            const uint32_t slot = primary(ent[q], R[0][q % 3] | (R[1][(q / 3) % 3] << 1) | (R[2][q / 9] << 2), lev0);
             if ((hit >> q) & 1u) {
-                const uint32_t slot = leaf & (S - 1);
                 atomicAdd(&vals[3 * slot], a0);
                 atomicAdd(&vals[3 * slot + 1], a1);
                 atomicAdd(&vals[3 * slot + 2], a2);
             } else {
-                add_probing(leaf, a0, a1, a2);
+                add_probing(leaf, slot, a0, a1, a2);
             }
         }
     }
@@ -444,7 +461,7 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
                     if ((st.valid & need) != need) live &= ~(1u << q);
                 }
             }
-            sink.add27(ent, live, st.w, F);
+            sink.add27(ent, live, st.w, F, st.R, tv.lev[0]);
         }
     }
     if (OPS & kOpInterp) {
