@@ -272,6 +272,12 @@ void set_error(const std::string &msg);
 // LDS-staged LSD radix sort of (uint64 key, int32 value) pairs.
 int64_t scan_tmp_words(int64_t n);
 void exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+// The same scan without its last pass: out holds every 2048-value block's
+// own exclusive scan and the result the blocks' scanned sums (element i's
+// prefix is out[i] + result[i / 2048]); nullptr when out already holds the
+// whole scan (one block, or more than 2048 blocks).
+const uint32_t *exclusive_scan_split(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+constexpr int64_t kScanBlock = 2048;
 int64_t radix_ws_bytes(int64_t n);
 void radix_sort_pairs(uint64_t *k0, int32_t *v0, uint64_t *k1, int32_t *v1, int64_t n, int bits, void *ws,
                       uint64_t **k_res, int32_t **v_res, hipStream_t s);

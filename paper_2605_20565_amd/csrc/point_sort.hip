@@ -224,7 +224,8 @@ template <typename T, int R>
 __global__ __launch_bounds__(kThreads) void k_point_scatter(
     const uint64_t *__restrict__ kin, const T *__restrict__ rin, const T *__restrict__ pos,
     const T *__restrict__ force, uint64_t *__restrict__ kout, T *__restrict__ rout, int64_t n, int shift,
-    const uint32_t *__restrict__ offs, int nblocks, unsigned long long *__restrict__ maxbits, int first)
+    const uint32_t *__restrict__ offs, const uint32_t *__restrict__ offs_hi, int nblocks,
+    unsigned long long *__restrict__ maxbits, int first)
 {
     __shared__ uint32_t sk[kPadded];
     __shared__ uint16_t si[kPadded];
@@ -382,7 +383,8 @@ __global__ __launch_bounds__(kThreads) void k_point_scatter(
         const int i = j * kThreads + threadIdx.x;
         const uint32_t key = sk[pad(i)];
         const uint32_t d = ((key & kIdMask) >> shift) & (kBuckets - 1);
-        const int64_t o = (int64_t)offs[(int64_t)d * nblocks + tile];
+        const int64_t oi = (int64_t)d * nblocks + tile;
+        const int64_t o = (int64_t)offs[oi] + (offs_hi ? (int64_t)offs_hi[oi / kScanBlock] : 0);
         dstv[j] = i < valid ? o + (i - (int)dstart[d]) : -1;
         srcv[j] = i < valid ? (int)si[pad(i)] : 0;
     }
@@ -448,9 +450,11 @@ void sort_passes(const TreeView &tv, int64_t n, int64_t n_leaves, int shift, int
     for (int sh = 0; sh < bits; sh += kBits) {
         const int o = cur ^ 1;   // write buffer: 1, 0, 1, ...
         if (sh > 0) hipLaunchKernelGGL(k_point_hist, dim3(nb), dim3(kThreads), 0, s, kin, n, shift + sh, counts, nb);
-        exclusive_scan(counts, offs, nc, tmp, s);
+        // the digit offsets: each 2048-count block's own scan, plus the
+        // blocks' scanned sums, which the scatter adds (one launch less)
+        const uint32_t *offs_hi = exclusive_scan_split(counts, offs, nc, tmp, s);
         hipLaunchKernelGGL((k_point_scatter<T, R>), dim3(nb), dim3(kThreads), 0, s, kin, rin, pos, force, b.kv[o],
-                           b.rec[o], n, shift + sh, (const uint32_t *)offs, nb,
+                           b.rec[o], n, shift + sh, (const uint32_t *)offs, offs_hi, nb,
                            sh == 0 ? maxbits : (unsigned long long *)nullptr, sh == 0 ? 1 : 0);
         kin = b.kv[o];
         rin = b.rec[o];

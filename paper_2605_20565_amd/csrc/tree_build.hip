@@ -116,6 +116,20 @@ void exclusive_scan(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp,
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, n, sums_scan);
 }
 
+const uint32_t *exclusive_scan_split(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s)
+{
+    static_assert(kScanBlock == kSortTile, "the split scan's block is the scan tile");
+    const int64_t nb = (n + kSortTile - 1) / kSortTile;
+    if (nb <= 1 || nb > kSortTile) {
+        exclusive_scan(in, out, n, tmp, s);
+        return nullptr;
+    }
+    uint32_t *sums = tmp, *sums_scan = tmp + nb;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kSortThreads), 0, s, in, out, n, sums);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kSortThreads), 0, s, sums, sums_scan, nb, (uint32_t *)nullptr);
+    return sums_scan;
+}
+
 // -- LSD radix sort of (uint64 key, int32 value), 8 bits per pass ------------
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
                                                              uint32_t *__restrict__ counts, int nblocks)
