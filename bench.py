@@ -4,7 +4,7 @@
 One step = host-cell search + interpolation + spreading of every point of the
 workload (8 bubbles' markers and 10^7 uniform particles on a band-refined
 l 7->10 octree, FP32, fixed-point spreading) in one batched persistent pass
-(with the in-step sort: 14 kernels on one stream).  Inputs are resident in
+(with the in-step sort: 12 kernels on one stream).  Inputs are resident in
 HBM before timing starts.
 
 Prints one JSON line: points/s, the dominant kernel's achieved bandwidth

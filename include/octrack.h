@@ -157,9 +157,10 @@ typedef struct {
 #define OT_TUNE_HOST_MAJOR 2
 
 /* Replay the plan's kernels through a captured HIP graph: one graph launch
- * per run instead of the plan's 4 to 14 kernel launches, which saves host
- * time per run.  Off by default: on this GPU the graph launch made a run
- * about 7 us longer on 11 k points and no faster on 10^7. */
+ * per run instead of the plan's kernel launches (4 without point sorting,
+ * 12 with it up to about 33 M points and 4 M leaves, more above), which
+ * saves host time per run.  Off by default: on this GPU the graph launch
+ * made a run about 7 us longer on 11 k points and no faster on 10^7. */
 #define OT_TUNE_GRAPH 4
 
 /* Morton keys of leaf anchors (Sec. 3.1: leaves are ordered along the
