@@ -407,24 +407,29 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
                     v[d] = Fpre ? Fpre[d] : force[kp + d];
                 }
             }
-            // the gathers of one z-plane of the stencil (nine rows) are issued
-            // together before any is used (the scheduler had kept about six in
-            // flight); a node dropped at a wall has entry 0 and loads row 0
+            // the gathers are issued in two batches (rows 0-13, then 14-26),
+            // each loaded before any of its rows is used (the scheduler had
+            // kept about six in flight); a node dropped at a wall has entry 0
+            // and loads row 0
 #pragma unroll
-            for (int oz = 0; oz < 3; ++oz) {
-                T fr[9][3];
+            for (int b = 0; b < 2; ++b) {
+                constexpr int kB = 14;
+                const int q0 = b * kB, nq = b ? 27 - kB : kB;
+                T fr[kB][3];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const int64_t j = 3 * (int64_t)(ent[9 * oz + i] & kIdMask);
+                for (int i = 0; i < kB; ++i) {
+                    if (i >= nq) break;
+                    const int64_t j = 3 * (int64_t)(ent[q0 + i] & kIdMask);
                     fr[i][0] = field[j];
                     fr[i][1] = field[j + 1];
                     fr[i][2] = field[j + 2];
                 }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const int q = 9 * oz + i;
-                    const int ox = q % 3, oy = (q / 3) % 3;
+                for (int i = 0; i < kB; ++i) {
+                    if (i >= nq) break;
+                    const int q = q0 + i;
+                    const int ox = q % 3, oy = (q / 3) % 3, oz = q / 9;
                     const uint32_t need = (1u << ox) | (1u << (3 + oy)) | (1u << (6 + oz));
                     if (!PER && (st.valid & need) != need) continue;
                     const T f0 = fr[i][0], f1 = fr[i][1], f2 = fr[i][2];
