@@ -407,14 +407,15 @@ __device__ __forceinline__ void track_point_at(const TreeView &tv, int64_t k, bo
                     v[d] = Fpre ? Fpre[d] : force[kp + d];
                 }
             }
-            // the gathers are issued in two batches (rows 0-13, then 14-26),
-            // each loaded before any of its rows is used (the scheduler had
-            // kept about six in flight); a node dropped at a wall has entry 0
-            // and loads row 0
+            // the gathers are issued in batches of kB rows (FP32: 14 and 13;
+            // FP64, whose rows take twice the registers: three of 9), each
+            // loaded before any of its rows is used (the scheduler had kept
+            // about six in flight); a node dropped at a wall has entry 0 and
+            // loads row 0
+            constexpr int kB = sizeof(T) == 4 ? 14 : 9;
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                constexpr int kB = 14;
-                const int q0 = b * kB, nq = b ? 27 - kB : kB;
+            for (int b = 0; b < (27 + kB - 1) / kB; ++b) {
+                const int q0 = b * kB, nq = 27 - q0 < kB ? 27 - q0 : kB;
                 T fr[kB][3];
 #pragma unroll
                 for (int i = 0; i < kB; ++i) {
